@@ -1,0 +1,203 @@
+"""Benchmark: 4K frames/s at N_max = 200 on one MI355X.
+
+Workload: batches of 3840 x 2160 FP32 frames (inscribed disk of diameter
+2160 px), every Zernike moment up to n_max = 200 (10201 complex moments per
+frame) on a 1080-ring x 4096-angle polar grid.  One step = the whole hot path
+over one batch: fused resample + angular FFT (zm_spectra), then the radial
+projection on the matrix cores (zm_project).  Frames are device resident
+before the timed region starts.
+
+Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
+  roofline       resample+FFT kernel: algorithmic bytes per launch / average
+                 launch duration (HIP events on the launch stream) vs 8 TB/s
+  projection     the projection kernel's useful FLOP rate vs the MFMA peak
+  split_bf16     the same step with the hi/lo split-BF16 projection
+  cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+H, W = 2160, 3840
+NMAX, RINGS, ANGLES = 200, 1080, 4096
+DISTINCT = 4          # distinct seeded frames (seeds 3..6), tiled to fill the batch
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0}
+METRIC = "4K images/s at N_max=200 (FP32 vs split-BF16) + p50/p99 latency at fixed QPS"
+
+
+def disk_pixels(h, w):
+    d = min(h, w)
+    X = 2 * np.arange(w, dtype=np.int64) - (w - 1)
+    Y = (h - 1) - 2 * np.arange(h, dtype=np.int64)
+    return int(np.count_nonzero(X[None, :] ** 2 + Y[:, None] ** 2 <= d * d))
+
+
+def spectra_bytes_per_frame():
+    # algorithmic traffic of the fused resample+FFT: every pixel of the disk
+    # footprint read once (FP32) + the ring spectra written once (FP32 complex,
+    # n_max + 1 bins per ring)
+    return 4 * disk_pixels(H, W) + (NMAX + 1) * 2 * RINGS * 4
+
+
+def projection_flops_per_frame():
+    # useful work: 2 (re, im) x 2 flops per multiply-add, over rings, per moment
+    return 4 * RINGS * ((NMAX // 2 + 1) ** 2)
+
+
+def make_frames(batch):
+    import synth
+    from synth.frames import FrameSpec
+    spec = FrameSpec(H, W, blobs=32, polygons=16, noise=False, zero_outside=False)
+    base = [synth.make_frame(spec, 3 + i) for i in range(min(DISTINCT, batch))]
+    return base
+
+
+def run_gpu(batch, steps, warmup, dtype):
+    import torch
+    import paper_2304_14492_amd as zm
+    plan = zm.Plan(NMAX, H, W, dtype=dtype, rings=RINGS, angles=ANGLES)
+    base = make_frames(batch)
+    frames = torch.empty(batch, H, W, dtype=torch.float32, device="cuda")
+    for i in range(batch):
+        frames[i].copy_(torch.from_numpy(base[i % len(base)]))
+    ws = plan.workspace(batch)
+    Z = torch.empty(batch, plan.num_moments, 2, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        plan.spectra(frames, ws, stream)
+        if ev is not None:
+            ev[1].record(stream)
+        plan.project(batch, Z, ws, stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    for k in range(steps):
+        step(evs[k])
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t0.elapsed_time(t1)
+    spec_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    proj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    out = dict(total_ms=total_ms, wall_s=wall, spec_ms=spec_ms, proj_ms=proj_ms, Z=Z, plan=plan)
+    return out
+
+
+def cpu_baseline(budget_s):
+    """FP64 oracle (resample + angular DFT + radial sum per frame; the exact
+    radial table is plan-time work and is built once, untimed) on 4K frames."""
+    import oracle
+    import synth
+    from synth.frames import FrameSpec
+    spec = FrameSpec(H, W, blobs=32, polygons=16, noise=False, zero_outside=False)
+    f = synth.make_frame(spec, 3).astype(np.float64)
+    grid = oracle.ring_grid(RINGS)
+    pl = oracle.pairs(NMAX)
+    table = oracle.zrp(pl, grid)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.moments(f, NMAX, RINGS, ANGLES, plist=pl, table=table)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 50:
+            break
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n / el, unit="images/s", cores=min(cores, os.cpu_count() or cores), kind="oracle",
+                sample=f"{n} full 3840x2160 frame(s) at N_max=200 (all 10201 moments), {el:.1f} s; "
+                       "exact radial table built once beforehand (plan-time, untimed)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16x2", "f16x2"])
+    ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 comparison run")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="0 skips the CPU baseline")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: every frame is independent (images shard with no "
+              "communication), and multi-GPU runs are not part of this build; use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    print(f"[bench] batch={args.batch} steps={args.steps} warmup={args.warmup} dtype={args.dtype}",
+          file=sys.stderr, flush=True)
+    r = run_gpu(args.batch, args.steps, args.warmup, args.dtype)
+    ms = r["total_ms"] / args.steps
+    value = args.batch / (ms / 1e3)
+    bytes_launch = spectra_bytes_per_frame() * args.batch
+    achieved = bytes_launch / (r["spec_ms"] / 1e3) / 1e9
+    flops_launch = projection_flops_per_frame() * args.batch
+    proj_tflops = flops_launch / (r["proj_ms"] / 1e3) / 1e12
+    print(f"[bench] {args.dtype}: {ms:.3f} ms/step, spectra {r['spec_ms']:.3f} ms, projection "
+          f"{r['proj_ms']:.3f} ms", file=sys.stderr, flush=True)
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.dtype == "f32" else args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"{W}x{H} FP32 frames (32 blobs + 16 polygons), N_max={NMAX} (10201 moments), "
+                               f"{RINGS} rings x {ANGLES} angles, batch {args.batch}",
+                   "batch": args.batch, "frame": [H, W], "n_max": NMAX, "rings": RINGS, "angles": ANGLES,
+                   "projection": args.dtype},
+        "roofline": {"bound": "hbm", "kernel": "polar_fft_kernel (fused resample + angular FFT)",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": bytes_launch, "avg_launch_ms": round(r["spec_ms"], 4)},
+        "projection": {"kernel": "project_kernel", "avg_launch_ms": round(r["proj_ms"], 4),
+                       "useful_tflops": round(proj_tflops, 2), "peak_tflops": MFMA_PEAK_TFLOPS[args.dtype],
+                       "frac": round(proj_tflops / MFMA_PEAK_TFLOPS[args.dtype], 4)},
+    }
+    if not args.no_split and args.dtype == "f32":
+        del r
+        torch.cuda.empty_cache()
+        r2 = run_gpu(args.batch, args.steps, args.warmup, "bf16x2")
+        ms2 = r2["total_ms"] / args.steps
+        res["split_bf16"] = {"value": round(args.batch / (ms2 / 1e3), 2), "unit": "images/s",
+                             "ms_per_step": round(ms2, 4), "projection_ms": round(r2["proj_ms"], 4),
+                             "projection_useful_tflops": round(flops_launch / (r2["proj_ms"] / 1e3) / 1e12, 2)}
+        print(f"[bench] bf16x2: {ms2:.3f} ms/step, projection {r2['proj_ms']:.3f} ms", file=sys.stderr, flush=True)
+    if args.cpu_seconds > 0:
+        print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

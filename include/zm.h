@@ -1,0 +1,162 @@
+/*
+ * zm.h -- C ABI of libzm: Zernike moments on AMD Instinct MI355X (gfx950).
+ *
+ * Computes every Zernike moment Z_nm (0 <= n <= n_max, 0 <= m <= n, n - m
+ * even) of eq. (1) of Al-Rawi, "Ultra-Fast Zernike Moments using FFT and GPU"
+ * (arXiv 2304.14492), for batches of frames:
+ *
+ *   Z_nm = (n+1)/(pi eps_m) * sum_r w_r R_nm(rho_r) * (2 pi / A) * sum_a f^(rho_r, theta_a) exp(-j m theta_a)
+ *
+ * on an R-ring x A-angle polar grid over the frame's inscribed disk, with the
+ * radial polynomials R_nm taken from the DFT relation eq. (7) (Chebyshev-U
+ * samples transformed over angle, Sec. 2.1) and eps_m the optional Neumann
+ * factor of eq. (14)-(15) (eps_0 = 2, else 1; 1 when normalisation is off).
+ * Moments with m < 0 follow from Z_{n,-m} = conj(Z_nm) (Sec. 2) and are not
+ * stored.
+ *
+ * Geometry (all entry points): a frame is H x W row-major; the unit disk is
+ * the inscribed disk of radius D/2 pixels, D = min(H, W), centred at
+ * ((W-1)/2, (H-1)/2) in pixel-centre coordinates; x points right, y up,
+ * theta counter-clockwise.  The polar sample (r, a) sits at rho_r,
+ * theta_a = 2 pi a / A, and takes the bilinear interpolation of the four
+ * surrounding pixels; pixels outside the frame count as 0 (Sec. 2.5).
+ *
+ * Canonical moment order: n ascending, then m ascending over m = n mod 2,
+ * n mod 2 + 2, ..., n; zm_index(n, m) gives the position.
+ *
+ * Conventions: every call returns a zm_status; no exception or signal
+ * crosses the ABI.  Argument checks are synchronous.  Device work is
+ * enqueued on the caller's HIP stream and returns before it completes;
+ * a fault in it surfaces at the caller's next synchronisation (and as
+ * ZM_EDEVICE from the next call that synchronises).  zm_last_error()
+ * returns a thread-local description of the most recent failure.
+ */
+#ifndef ZM_H_
+#define ZM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct zm_plan_s* zm_plan_t; /* opaque; owns the resident device tables */
+typedef void* zm_stream_t;           /* a hipStream_t; NULL means the null stream */
+
+typedef enum {
+    ZM_OK = 0,
+    ZM_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad combination) */
+    ZM_ENOMEM = -2,       /* device or host allocation failed */
+    ZM_EDEVICE = -3,      /* a HIP runtime call failed */
+    ZM_EUNSUPPORTED = -4, /* valid request outside what the kernels support */
+    ZM_EBUSY = -5         /* resource in use */
+} zm_status;
+
+/* Arithmetic of the radial projection (the dense contraction over rings).
+ * The radial tables are always generated in FP64.
+ *   ZM_F64    : FP64 frames, FP64 resampling / FFT / projection; FP64 moments.
+ *   ZM_F32    : FP32 frames, FP32 resampling / FFT / projection; FP32 moments.
+ *   ZM_BF16X2 : as ZM_F32, but the projection splits both operands into
+ *               hi + lo bfloat16 parts (three products, FP32 accumulation).
+ *   ZM_F16X2  : as ZM_BF16X2 with IEEE half parts (operands scaled by powers
+ *               of two per table row and per frame to stay in half range). */
+typedef enum { ZM_F64 = 0, ZM_F32 = 1, ZM_BF16X2 = 2, ZM_F16X2 = 3 } zm_dtype;
+
+/* Radial quadrature of eq. (1):
+ *   ZM_RING_MIDPOINT       : rho_r = (2r+1)/(2R), w_r = rho_r / R (uniform rings);
+ *   ZM_RING_GAUSS_LEGENDRE : Gauss-Legendre nodes mapped to [0, 1], w_r = w_GL,r rho_r / 2. */
+typedef enum { ZM_RING_MIDPOINT = 0, ZM_RING_GAUSS_LEGENDRE = 1 } zm_ring_rule;
+
+typedef struct {
+    int n_max;         /* maximum order, 0..500 (moments: 0..255)                      */
+    int H, W;          /* frame rows, cols (>= 2 each)                                 */
+    zm_dtype dtype;
+    int neumann;       /* nonzero: divide by eps_m (eq. (14)-(15))                     */
+    int rings;         /* R; 0 selects floor(D/2)                                      */
+    int angles;        /* A; 0 selects pow2ceil(max(2 n_max + 2, ceil(pi R), 32))      */
+    zm_ring_rule rule;
+    int device;        /* HIP device ordinal; -1 selects the current device            */
+} zm_plan_desc;
+
+typedef struct {
+    int n_max, H, W, rings, angles, num_moments;
+    int rings_padded;                 /* R rounded up to the projection's K step        */
+    zm_dtype dtype;
+    int neumann;
+    zm_ring_rule rule;
+    int device;
+    size_t resident_bytes;            /* device memory owned by the plan                */
+    size_t workspace_bytes_per_image; /* spectrum workspace one frame needs             */
+    size_t workspace_bytes_fixed;     /* per-call workspace independent of batch        */
+} zm_plan_info_t;
+
+/* Number of stored moments for n_max: (n_max/2+1)(n_max/2+1) for even n_max,
+ * (n_max+1)(n_max+3)/4 for odd n_max; -1 if n_max < 0. */
+int zm_num_moments(int n_max);
+
+/* Canonical position of (n, m): off(n) + m/2 with off(2p) = p(p+1),
+ * off(2p+1) = (p+1)^2; -1 if n < 0, m < 0, m > n or n - m odd. */
+int zm_index(int n, int m);
+
+/* Create a plan with the default polar grid (midpoint rings, R and A as in
+ * zm_plan_desc) on the current device.  Builds the FP64 radial table of
+ * eq. (7) on the device, folds the quadrature weights and (n+1)/(pi eps_m)
+ * into the projection operand, and keeps everything resident.  Synchronous.
+ * out receives the plan (caller destroys it with zm_destroy). */
+zm_status zm_plan(int n_max, int H, int W, zm_dtype dtype, int neumann, zm_plan_t* out);
+
+/* As zm_plan with an explicit descriptor (R, A, ring rule, device).
+ * Constraints: 1 <= R <= 4096; A a power of two with 32 <= A <= 4096 and
+ * A >= 2 n_max + 2.  n_max > 255 plans only serve zm_radial_table
+ * (zm_moments then returns ZM_EUNSUPPORTED). */
+zm_status zm_plan_ex(const zm_plan_desc* desc, zm_plan_t* out);
+
+zm_status zm_plan_info(zm_plan_t plan, zm_plan_info_t* out);
+
+/* Copy the FP64 radial table R_nm(rho_r) produced by eq. (7) (unweighted) to
+ * host memory: host_out[idx * R + r], idx canonical.  n_elems must be at
+ * least num_moments * R.  Synchronous. */
+zm_status zm_radial_table(zm_plan_t plan, double* host_out, size_t n_elems);
+
+/* Copy the plan's ring nodes rho_r and weights w_r (FP64, R each) to host. */
+zm_status zm_ring_nodes(zm_plan_t plan, double* rho_out, double* w_out, size_t n_elems);
+
+/* Bytes of device workspace zm_moments needs for `batch` frames. */
+zm_status zm_workspace_size(zm_plan_t plan, int batch, size_t* bytes);
+
+/* Moments of `batch` frames (asynchronous on `stream`).
+ *   d_images : device pointer, frame b at d_images + b * image_stride elements,
+ *              each H x W row-major; float (FP32 dtypes) or double (ZM_F64).
+ *              Only pixels within D/2 + 1.5 px of the centre are read.
+ *   d_Z      : device pointer, [batch][num_moments][2] (re, im), float or double.
+ *   d_ws     : device workspace of ws_bytes >= zm_workspace_size(plan, batch).
+ * Overlapping calls on one plan are safe when they use distinct workspaces. */
+zm_status zm_moments(zm_plan_t plan, const void* d_images, int batch, long long image_stride,
+                     void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream);
+
+/* The two stages of zm_moments, for callers that want the ring spectra or
+ * time the stages separately.  zm_spectra runs the fused resample + angular
+ * FFT and leaves F_r[m] = sum_a f^(rho_r, theta_a) exp(-2 pi i m a / A) for
+ * m = 0..n_max in the workspace (layout [batch][m][re|im][rings_padded],
+ * FP32, or FP64 for ZM_F64); zm_project applies the radial projection to the
+ * spectra of a preceding zm_spectra call on the same workspace and stream.
+ * zm_moments == zm_spectra followed by zm_project. */
+zm_status zm_spectra(zm_plan_t plan, const void* d_images, int batch, long long image_stride, void* d_ws,
+                     size_t ws_bytes, zm_stream_t stream);
+zm_status zm_project(zm_plan_t plan, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream);
+
+/* Moments from a polar image already on the grid (bypasses the resampler):
+ * d_polar is [batch][R][A] (float, or double for ZM_F64). */
+zm_status zm_moments_polar(zm_plan_t plan, const void* d_polar, int batch, void* d_Z, void* d_ws,
+                           size_t ws_bytes, zm_stream_t stream);
+
+zm_status zm_destroy(zm_plan_t plan);
+
+const char* zm_status_str(zm_status s);
+const char* zm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZM_H_ */

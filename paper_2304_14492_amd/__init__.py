@@ -1,0 +1,238 @@
+"""Python binding of libzm (Zernike moments on MI355X / gfx950).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/zm.h``.  PyTorch supplies
+device memory and the HIP stream.  There is no CPU fallback: if the built
+library is missing, importing this package raises.
+
+Typical use::
+
+    import torch, paper_2304_14492_amd as zm
+    plan = zm.Plan(200, 2160, 3840, dtype="f32")
+    frames = torch.rand(8, 2160, 3840, device="cuda")
+    Z = plan.moments(frames)            # [8, num_moments, 2] float32 (re, im)
+    Zc = zm.as_complex(Z)               # complex view, canonical (n, m) order
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libzm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"libzm.so is not built ({LIB_PATH}); run `python -c 'import __graft_entry__ as g; g.build()'` "
+        "or `python paper_2304_14492_amd/_build.py` first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+ZM_OK, ZM_EINVAL, ZM_ENOMEM, ZM_EDEVICE, ZM_EUNSUPPORTED, ZM_EBUSY = 0, -1, -2, -3, -4, -5
+DTYPES = {"f64": 0, "f32": 1, "bf16x2": 2, "f16x2": 3}
+RULES = {"midpoint": 0, "gauss_legendre": 1}
+
+
+class zm_plan_desc(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int), ("H", ctypes.c_int), ("W", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("neumann", ctypes.c_int), ("rings", ctypes.c_int), ("angles", ctypes.c_int),
+                ("rule", ctypes.c_int), ("device", ctypes.c_int)]
+
+
+class zm_plan_info_t(ctypes.Structure):
+    _fields_ = [("n_max", ctypes.c_int), ("H", ctypes.c_int), ("W", ctypes.c_int), ("rings", ctypes.c_int),
+                ("angles", ctypes.c_int), ("num_moments", ctypes.c_int), ("rings_padded", ctypes.c_int),
+                ("dtype", ctypes.c_int), ("neumann", ctypes.c_int), ("rule", ctypes.c_int),
+                ("device", ctypes.c_int), ("resident_bytes", ctypes.c_size_t),
+                ("workspace_bytes_per_image", ctypes.c_size_t), ("workspace_bytes_fixed", ctypes.c_size_t)]
+
+
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_SIGS = {
+    "zm_num_moments": (ctypes.c_int, [ctypes.c_int]),
+    "zm_index": (ctypes.c_int, [ctypes.c_int, ctypes.c_int]),
+    "zm_plan": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                               ctypes.POINTER(_vp)]),
+    "zm_plan_ex": (ctypes.c_int, [ctypes.POINTER(zm_plan_desc), ctypes.POINTER(_vp)]),
+    "zm_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(zm_plan_info_t)]),
+    "zm_radial_table": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _sz]),
+    "zm_ring_nodes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _sz]),
+    "zm_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_sz)]),
+    "zm_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp, _sz, _vp]),
+    "zm_moments_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "zm_spectra": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _sz, _vp]),
+    "zm_project": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "zm_destroy": (ctypes.c_int, [_vp]),
+    "zm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
+    "zm_last_error": (ctypes.c_char_p, []),
+}
+for _name, (_res, _args) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+class ZmError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _lib.zm_status_str(status).decode() + ": " + _lib.zm_last_error().decode()
+        super().__init__(f"{where}: {msg}")
+
+
+def _check(st: int, where: str):
+    if st != ZM_OK:
+        raise ZmError(st, where)
+
+
+def num_moments(n_max: int) -> int:
+    return _lib.zm_num_moments(n_max)
+
+
+def index(n: int, m: int) -> int:
+    return _lib.zm_index(n, m)
+
+
+def exported_symbols():
+    return list(_SIGS)
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A resident plan: polar grid, FP64 radial table (eq. (7)) and the
+    projection operand, for frames of one size and one n_max."""
+
+    def __init__(self, n_max: int, H: int, W: int, dtype: str = "f32", neumann: bool = False,
+                 rings: int = 0, angles: int = 0, rule: str = "midpoint", device: int = -1):
+        d = zm_plan_desc(n_max, H, W, DTYPES[dtype], int(bool(neumann)), rings, angles, RULES[rule], device)
+        h = _vp()
+        _check(_lib.zm_plan_ex(ctypes.byref(d), ctypes.byref(h)), "zm_plan_ex")
+        self._h = h
+        self.dtype = dtype
+        info = zm_plan_info_t()
+        _check(_lib.zm_plan_info(h, ctypes.byref(info)), "zm_plan_info")
+        self.info = info
+        self.n_max, self.H, self.W = info.n_max, info.H, info.W
+        self.rings, self.angles, self.num_moments = info.rings, info.angles, info.num_moments
+        self.rings_padded = info.rings_padded
+        self.neumann = bool(info.neumann)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.zm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def radial_table(self):
+        import numpy as np
+        out = np.empty((self.num_moments, self.rings), dtype=np.float64)
+        _check(_lib.zm_radial_table(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
+               "zm_radial_table")
+        return out
+
+    def ring_nodes(self):
+        import numpy as np
+        rho = np.empty(self.rings, dtype=np.float64)
+        w = np.empty(self.rings, dtype=np.float64)
+        _check(_lib.zm_ring_nodes(self._h, rho.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                  w.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), self.rings), "zm_ring_nodes")
+        return rho, w
+
+    def workspace_size(self, batch: int) -> int:
+        n = _sz()
+        _check(_lib.zm_workspace_size(self._h, batch, ctypes.byref(n)), "zm_workspace_size")
+        return n.value
+
+    def _real_dtype(self):
+        import torch
+        return torch.float64 if self.dtype == "f64" else torch.float32
+
+    def workspace(self, batch: int, device=None):
+        import torch
+        return torch.empty(self.workspace_size(batch), dtype=torch.uint8, device=device or "cuda")
+
+    def moments(self, frames, out=None, workspace=None, stream=None):
+        """frames: CUDA tensor [B, H, W] (or [H, W]) of float32 (float64 for
+        dtype "f64"), rows contiguous.  Returns [B, num_moments, 2] (re, im)."""
+        import torch
+        squeeze = frames.dim() == 2
+        if squeeze:
+            frames = frames.unsqueeze(0)
+        if frames.dim() != 3 or frames.shape[1] != self.H or frames.shape[2] != self.W:
+            raise ValueError(f"expected frames of shape [B, {self.H}, {self.W}], got {tuple(frames.shape)}")
+        if frames.dtype != self._real_dtype() or not frames.is_cuda:
+            raise ValueError(f"frames must be a CUDA {self._real_dtype()} tensor")
+        if frames.stride(2) != 1 or frames.stride(1) != self.W:
+            raise ValueError("frame rows must be contiguous")
+        B = frames.shape[0]
+        if out is None:
+            out = torch.empty(B, self.num_moments, 2, dtype=self._real_dtype(), device=frames.device)
+        if workspace is None:
+            workspace = self.workspace(B, frames.device)
+        st = _lib.zm_moments(self._h, _vp(frames.data_ptr()), B, frames.stride(0) if B > 1 else self.H * self.W,
+                             _vp(out.data_ptr()), _vp(workspace.data_ptr()), workspace.numel(),
+                             _stream_handle(stream))
+        _check(st, "zm_moments")
+        return out[0] if squeeze else out
+
+    def _check_frames(self, frames):
+        if frames.dim() != 3 or frames.shape[1] != self.H or frames.shape[2] != self.W:
+            raise ValueError(f"expected frames of shape [B, {self.H}, {self.W}], got {tuple(frames.shape)}")
+        if frames.dtype != self._real_dtype() or not frames.is_cuda:
+            raise ValueError(f"frames must be a CUDA {self._real_dtype()} tensor")
+        if frames.stride(2) != 1 or frames.stride(1) != self.W:
+            raise ValueError("frame rows must be contiguous")
+
+    def spectra(self, frames, workspace, stream=None):
+        """Stage 1 only: ring spectra of frames [B, H, W] into `workspace`."""
+        self._check_frames(frames)
+        B = frames.shape[0]
+        _check(_lib.zm_spectra(self._h, _vp(frames.data_ptr()), B,
+                               frames.stride(0) if B > 1 else self.H * self.W, _vp(workspace.data_ptr()),
+                               workspace.numel(), _stream_handle(stream)), "zm_spectra")
+
+    def project(self, batch, out, workspace, stream=None):
+        """Stage 2 only: moments of the spectra left in `workspace` by spectra()."""
+        _check(_lib.zm_project(self._h, batch, _vp(out.data_ptr()), _vp(workspace.data_ptr()),
+                               workspace.numel(), _stream_handle(stream)), "zm_project")
+        return out
+
+    def moments_polar(self, polar, out=None, workspace=None, stream=None):
+        """polar: CUDA tensor [B, rings, angles], contiguous."""
+        import torch
+        squeeze = polar.dim() == 2
+        if squeeze:
+            polar = polar.unsqueeze(0)
+        polar = polar.contiguous()
+        if polar.shape[1:] != (self.rings, self.angles) or polar.dtype != self._real_dtype():
+            raise ValueError("polar must be [B, rings, angles] of the plan's real dtype")
+        B = polar.shape[0]
+        if out is None:
+            out = torch.empty(B, self.num_moments, 2, dtype=self._real_dtype(), device=polar.device)
+        if workspace is None:
+            workspace = self.workspace(B, polar.device)
+        _check(_lib.zm_moments_polar(self._h, _vp(polar.data_ptr()), B, _vp(out.data_ptr()),
+                                     _vp(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)),
+               "zm_moments_polar")
+        return out[0] if squeeze else out
+
+
+def as_complex(Z):
+    """[..., num_moments, 2] real tensor -> complex tensor [..., num_moments]."""
+    import torch
+    return torch.view_as_complex(Z.contiguous())

@@ -1,0 +1,494 @@
+// Host side of libzm: argument checking, polar-grid geometry, resident
+// tables, workspace layout and the C entry points declared in zm.h.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "zm_internal.h"
+
+namespace zm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+
+zm_status fail(zm_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+zm_status hip_fail(hipError_t e, const char* what) {
+    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? ZM_ENOMEM : ZM_EDEVICE;
+}
+
+bool polar_fft_supported(zm_dtype dt, int A, int A2);
+
+static int pow2ceil(long v) {
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+// cos / sin(2 pi a / N), a = 0..N-1, N divisible by 8.  Only the first
+// octant is evaluated; the rest follows by the exact symmetries
+// (c, s) -> (s, c) about pi/4 and quarter-turn rotations, so samples a and
+// a + N/4 are exact 90-degree rotations of each other.
+static void unit_circle(int N, std::vector<double>& cs) {
+    cs.assign(2 * (size_t)N, 0.0);
+    const int q4 = N / 4;
+    const long double two_pi = 6.283185307179586476925286766559L;
+    for (int a = 0; a < N; ++a) {
+        const int qd = a / q4, b = a % q4;
+        double c, s;
+        if (2 * b <= q4) {
+            const long double t = two_pi * (long double)b / (long double)N;
+            c = (double)cosl(t);
+            s = (double)sinl(t);
+        } else {
+            const long double t = two_pi * (long double)(q4 - b) / (long double)N;
+            c = (double)sinl(t);
+            s = (double)cosl(t);
+        }
+        double cc = c, ss = s;
+        switch (qd) {
+            case 1: cc = -s; ss = c; break;
+            case 2: cc = -c; ss = -s; break;
+            case 3: cc = s; ss = -c; break;
+            default: break;
+        }
+        cs[2 * (size_t)a] = cc;
+        cs[2 * (size_t)a + 1] = ss;
+    }
+}
+
+// Gauss-Legendre nodes / weights on [-1, 1] (Newton on P_N in long double).
+static void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w) {
+    x.assign(N, 0.0);
+    w.assign(N, 0.0);
+    const long double pi = 3.141592653589793238462643383279L;
+    for (int i = 0; i < N; ++i) {
+        long double z = cosl(pi * ((long double)i + 0.75L) / ((long double)N + 0.5L));
+        long double dp = 1.0L;
+        for (int it = 0; it < 100; ++it) {
+            long double p0 = 1.0L, p1 = z;
+            for (int k = 2; k <= N; ++k) {
+                long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / (long double)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (N == 1) { p1 = z; p0 = 1.0L; }
+            dp = (long double)N * (z * p1 - p0) / (z * z - 1.0L);
+            long double dz = p1 / dp;
+            z -= dz;
+            if (fabsl(dz) < 1e-19L) break;
+        }
+        {
+            long double p0 = 1.0L, p1 = z;
+            for (int k = 2; k <= N; ++k) {
+                long double p2 = ((2.0L * k - 1.0L) * z * p1 - (k - 1.0L) * p0) / (long double)k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (N == 1) { p1 = z; p0 = 1.0L; }
+            dp = (long double)N * (z * p1 - p0) / (z * z - 1.0L);
+        }
+        x[N - 1 - i] = (double)z;  // ascending
+        w[N - 1 - i] = (double)(2.0L / ((1.0L - z * z) * dp * dp));
+    }
+}
+
+static void free_plan(zm_plan_s* p) {
+    if (!p) return;
+    void* bufs[] = {p->d_spx, p->d_trig, p->d_tw, p->d_table, p->d_thi,
+                    p->d_tlo, p->d_rowscale, p->d_items, p->d_rowmap};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    delete p;
+}
+
+template <typename T>
+static zm_status dev_alloc(T** ptr, size_t count, size_t* total) {
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void**)ptr, count * sizeof(T));
+    if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+    *total += count * sizeof(T);
+    return ZM_OK;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+static size_t spectrum_bytes(const zm_plan_s* p, int batch) {
+    const size_t el = p->dtype == ZM_F64 ? sizeof(double) : sizeof(float);
+    return (size_t)batch * (size_t)(p->n_max + 1) * 2 * (size_t)p->Rp * el;
+}
+
+static size_t workspace_bytes(const zm_plan_s* p, int batch) {
+    size_t b = align256(spectrum_bytes(p, batch));
+    if (p->dtype == ZM_F16X2) b += align256((size_t)batch * sizeof(float));
+    return b;
+}
+
+static bool moments_supported(const zm_plan_s* p) {
+    return p->n_max <= kMaxMomentOrder && polar_fft_supported(p->dtype, p->A, p->A2);
+}
+
+}  // namespace zm
+
+using namespace zm;
+
+extern "C" {
+
+int zm_num_moments(int n_max) {
+    if (n_max < 0) return -1;
+    const int h = n_max / 2;
+    return (n_max % 2 == 0) ? (h + 1) * (h + 1) : (h + 1) * (h + 2);
+}
+
+int zm_index(int n, int m) {
+    if (n < 0 || m < 0 || m > n || ((n - m) & 1)) return -1;
+    return canon_index(n, m);
+}
+
+const char* zm_status_str(zm_status s) {
+    switch (s) {
+        case ZM_OK: return "ZM_OK";
+        case ZM_EINVAL: return "ZM_EINVAL: invalid argument";
+        case ZM_ENOMEM: return "ZM_ENOMEM: out of memory";
+        case ZM_EDEVICE: return "ZM_EDEVICE: HIP runtime error";
+        case ZM_EUNSUPPORTED: return "ZM_EUNSUPPORTED: unsupported configuration";
+        case ZM_EBUSY: return "ZM_EBUSY: resource busy";
+    }
+    return "unknown zm_status";
+}
+
+const char* zm_last_error(void) { return g_err.c_str(); }
+
+zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
+    if (!d || !out) return fail(ZM_EINVAL, "null descriptor or output pointer");
+    *out = nullptr;
+    if (d->n_max < 0 || d->n_max > kMaxTableOrder)
+        return fail(ZM_EINVAL, "n_max must be in [0, " + std::to_string(kMaxTableOrder) + "]");
+    if (d->H < 2 || d->W < 2) return fail(ZM_EINVAL, "frame must be at least 2 x 2");
+    if (d->dtype < ZM_F64 || d->dtype > ZM_F16X2) return fail(ZM_EINVAL, "unknown dtype");
+    if (d->rule != ZM_RING_MIDPOINT && d->rule != ZM_RING_GAUSS_LEGENDRE) return fail(ZM_EINVAL, "unknown ring rule");
+    const int D = std::min(d->H, d->W);
+    const int R = d->rings > 0 ? d->rings : D / 2;
+    if (d->rings < 0 || R < 1 || R > kMaxRings) return fail(ZM_EINVAL, "rings must be in [1, 4096]");
+    int A = d->angles;
+    if (A == 0) {
+        long need = std::max<long>(2L * d->n_max + 2, (long)std::ceil(M_PI * R));
+        A = pow2ceil(std::max<long>(need, kMinAngles));
+    }
+    if (A < kMinAngles || A > kMaxAngles || (A & (A - 1)) != 0)
+        return fail(ZM_EINVAL, "angles must be a power of two in [32, 4096]");
+    if (A < 2 * d->n_max + 2) return fail(ZM_EINVAL, "angles must be >= 2 n_max + 2");
+
+    int dev = d->device;
+    if (dev < 0) {
+        ZM_HIP(hipGetDevice(&dev));
+    } else {
+        int cnt = 0;
+        ZM_HIP(hipGetDeviceCount(&cnt));
+        if (dev >= cnt) return fail(ZM_EINVAL, "device ordinal out of range");
+        ZM_HIP(hipSetDevice(dev));
+    }
+
+    zm_plan_s* p = new zm_plan_s();
+    p->n_max = d->n_max;
+    p->H = d->H;
+    p->W = d->W;
+    p->D = D;
+    p->R = R;
+    p->A = A;
+    p->Rp = (R + kRingPad - 1) / kRingPad * kRingPad;
+    p->M = d->n_max + 1;
+    p->num_moments = zm_num_moments(d->n_max);
+    p->A2 = std::max(16, pow2ceil(d->n_max + 1));
+    p->NK = std::max(64, pow2ceil(2L * d->n_max + 2));
+    p->dtype = d->dtype;
+    p->neumann = d->neumann ? 1 : 0;
+    p->rule = d->rule;
+    p->device = dev;
+    p->cx = 0.5 * (d->W - 1);
+    p->cy = 0.5 * (d->H - 1);
+    p->rpx = 0.5 * D;
+
+    // ring nodes / weights of the radial quadrature of eq. (1)
+    std::vector<double> spx(R);
+    p->rho.resize(R);
+    p->w.resize(R);
+    if (d->rule == ZM_RING_MIDPOINT) {
+        for (int r = 0; r < R; ++r) {
+            p->rho[r] = (double)(2 * r + 1) / (double)(2 * R);
+            p->w[r] = (double)(2 * r + 1) / (2.0 * (double)R * (double)R);
+            spx[r] = (double)(2 * r + 1) * p->rpx / (double)(2 * R);
+        }
+    } else {
+        std::vector<double> x, wg;
+        gauss_legendre(R, x, wg);
+        for (int r = 0; r < R; ++r) {
+            p->rho[r] = 0.5 * (x[r] + 1.0);
+            p->w[r] = 0.5 * wg[r] * p->rho[r];
+            spx[r] = p->rho[r] * p->rpx;
+        }
+    }
+
+    // projection layout: m blocks of K_m rows (n = m, m+2, ..), padded to 16
+    p->blk_rows.resize(p->M);
+    p->blk_toff.resize(p->M);
+    int rows = 0;
+    std::vector<int> rowmap;
+    for (int m = 0; m <= p->n_max; ++m) {
+        const int km = (p->n_max - m) / 2 + 1;
+        const int padded = (km + kRowTile - 1) / kRowTile * kRowTile;
+        p->blk_rows[m] = km;
+        p->blk_toff[m] = rows;
+        for (int j = 0; j < padded; ++j) {
+            if (j < km) {
+                rowmap.push_back(canon_index(m + 2 * j, m));
+                rowmap.push_back(((m + 2 * j) << 16) | m);
+            } else {
+                rowmap.push_back(-1);
+                rowmap.push_back(0);
+            }
+        }
+        for (int r0 = 0; r0 < padded; r0 += 32) p->items.push_back(zm_item{m, r0, std::min(32, padded - r0), rows});
+        rows += padded;
+    }
+    p->table_rows = rows;
+
+    std::vector<double> trig, ck;
+    unit_circle(A, trig);
+    unit_circle(p->NK, ck);
+    std::vector<double> ckc(p->NK);
+    for (int k = 0; k < p->NK; ++k) ckc[k] = ck[2 * (size_t)k];
+
+    zm_status st = ZM_OK;
+    size_t total = 0;
+    double *d_rho = nullptr, *d_w = nullptr, *d_ck = nullptr;
+    auto cleanup_tmp = [&]() {
+        if (d_rho) (void)hipFree(d_rho);
+        if (d_w) (void)hipFree(d_w);
+        if (d_ck) (void)hipFree(d_ck);
+    };
+#define ZM_TRY(expr)                 \
+    do {                             \
+        st = (expr);                 \
+        if (st != ZM_OK) {           \
+            cleanup_tmp();           \
+            free_plan(p);            \
+            return st;               \
+        }                            \
+    } while (0)
+#define ZM_TRYHIP(call)                          \
+    do {                                         \
+        hipError_t e_ = (call);                  \
+        if (e_ != hipSuccess) ZM_TRY(hip_fail(e_, #call)); \
+    } while (0)
+
+    size_t scratch = 0;
+    ZM_TRY(dev_alloc(&d_rho, R, &scratch));
+    ZM_TRY(dev_alloc(&d_w, R, &scratch));
+    ZM_TRY(dev_alloc(&d_ck, p->NK, &scratch));
+    ZM_TRY(dev_alloc(&p->d_spx, R, &total));
+    ZM_TRY(dev_alloc(&p->d_trig, 2 * (size_t)A, &total));
+    ZM_TRY(dev_alloc(&p->d_table, (size_t)p->num_moments * R, &total));
+    const bool with_moments = moments_supported(p);
+    if (with_moments) {
+        const size_t n = (size_t)p->table_rows * p->Rp;
+        if (p->dtype == ZM_F64) {
+            double* t;
+            ZM_TRY(dev_alloc(&t, n, &total));
+            p->d_thi = t;
+            double* tw;
+            ZM_TRY(dev_alloc(&tw, 2 * (size_t)A, &total));
+            p->d_tw = tw;
+        } else {
+            if (p->dtype == ZM_F32) {
+                float* t;
+                ZM_TRY(dev_alloc(&t, n, &total));
+                p->d_thi = t;
+            } else {
+                uint16_t *th, *tl;
+                ZM_TRY(dev_alloc(&th, n, &total));
+                ZM_TRY(dev_alloc(&tl, n, &total));
+                p->d_thi = th;
+                p->d_tlo = tl;
+                if (p->dtype == ZM_F16X2) ZM_TRY(dev_alloc(&p->d_rowscale, (size_t)p->table_rows, &total));
+            }
+            float* tw;
+            ZM_TRY(dev_alloc(&tw, 2 * (size_t)A, &total));
+            p->d_tw = tw;
+        }
+        ZM_TRY(dev_alloc(&p->d_items, p->items.size(), &total));
+        ZM_TRY(dev_alloc(&p->d_rowmap, rowmap.size(), &total));
+    }
+
+    ZM_TRYHIP(hipMemcpy(d_rho, p->rho.data(), R * sizeof(double), hipMemcpyHostToDevice));
+    ZM_TRYHIP(hipMemcpy(d_w, p->w.data(), R * sizeof(double), hipMemcpyHostToDevice));
+    ZM_TRYHIP(hipMemcpy(d_ck, ckc.data(), p->NK * sizeof(double), hipMemcpyHostToDevice));
+    ZM_TRYHIP(hipMemcpy(p->d_spx, spx.data(), R * sizeof(double), hipMemcpyHostToDevice));
+    ZM_TRYHIP(hipMemcpy(p->d_trig, trig.data(), 2 * (size_t)A * sizeof(double), hipMemcpyHostToDevice));
+    if (with_moments) {
+        if (p->dtype == ZM_F64) {
+            ZM_TRYHIP(hipMemcpy(p->d_tw, trig.data(), 2 * (size_t)A * sizeof(double), hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> twf(2 * (size_t)A);
+            for (size_t i = 0; i < twf.size(); ++i) twf[i] = (float)trig[i];
+            ZM_TRYHIP(hipMemcpy(p->d_tw, twf.data(), twf.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
+        ZM_TRYHIP(hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(zm_item), hipMemcpyHostToDevice));
+        ZM_TRYHIP(hipMemcpy(p->d_rowmap, rowmap.data(), rowmap.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    {
+        hipError_t e = launch_zrp_table(p, d_rho, d_ck, nullptr);
+        if (e != hipSuccess) ZM_TRY(hip_fail(e, "zrp_table kernel launch"));
+        if (with_moments) {
+            e = launch_fold(p, d_w, nullptr);
+            if (e != hipSuccess) ZM_TRY(hip_fail(e, "fold kernel launch"));
+        }
+        e = hipStreamSynchronize(nullptr);
+        if (e != hipSuccess) ZM_TRY(hip_fail(e, "plan construction"));
+    }
+#undef ZM_TRY
+#undef ZM_TRYHIP
+    cleanup_tmp();
+    p->resident = total;
+    *out = p;
+    return ZM_OK;
+}
+
+zm_status zm_plan(int n_max, int H, int W, zm_dtype dtype, int neumann, zm_plan_t* out) {
+    zm_plan_desc d;
+    d.n_max = n_max;
+    d.H = H;
+    d.W = W;
+    d.dtype = dtype;
+    d.neumann = neumann;
+    d.rings = 0;
+    d.angles = 0;
+    d.rule = ZM_RING_MIDPOINT;
+    d.device = -1;
+    return zm_plan_ex(&d, out);
+}
+
+zm_status zm_plan_info(zm_plan_t p, zm_plan_info_t* o) {
+    if (!p || !o) return fail(ZM_EINVAL, "null plan or output");
+    o->n_max = p->n_max;
+    o->H = p->H;
+    o->W = p->W;
+    o->rings = p->R;
+    o->angles = p->A;
+    o->num_moments = p->num_moments;
+    o->rings_padded = p->Rp;
+    o->dtype = p->dtype;
+    o->neumann = p->neumann;
+    o->rule = p->rule;
+    o->device = p->device;
+    o->resident_bytes = p->resident;
+    o->workspace_bytes_per_image = align256(spectrum_bytes(p, 1));
+    o->workspace_bytes_fixed = p->dtype == ZM_F16X2 ? 256 : 0;
+    return ZM_OK;
+}
+
+zm_status zm_radial_table(zm_plan_t p, double* host_out, size_t n_elems) {
+    if (!p || !host_out) return fail(ZM_EINVAL, "null plan or output");
+    const size_t need = (size_t)p->num_moments * p->R;
+    if (n_elems < need) return fail(ZM_EINVAL, "output too small: need num_moments * rings elements");
+    ZM_HIP(hipSetDevice(p->device));
+    ZM_HIP(hipMemcpy(host_out, p->d_table, need * sizeof(double), hipMemcpyDeviceToHost));
+    return ZM_OK;
+}
+
+zm_status zm_ring_nodes(zm_plan_t p, double* rho_out, double* w_out, size_t n_elems) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (n_elems < (size_t)p->R) return fail(ZM_EINVAL, "output too small: need rings elements");
+    if (rho_out) std::memcpy(rho_out, p->rho.data(), p->R * sizeof(double));
+    if (w_out) std::memcpy(w_out, p->w.data(), p->R * sizeof(double));
+    return ZM_OK;
+}
+
+zm_status zm_workspace_size(zm_plan_t p, int batch, size_t* bytes) {
+    if (!p || !bytes) return fail(ZM_EINVAL, "null plan or output");
+    if (batch < 0) return fail(ZM_EINVAL, "negative batch");
+    *bytes = workspace_bytes(p, batch);
+    return ZM_OK;
+}
+
+static zm_status check_run(zm_plan_t p, int batch, void* d_ws, size_t ws_bytes) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch < 0) return fail(ZM_EINVAL, "negative batch");
+    if (!moments_supported(p))
+        return fail(ZM_EUNSUPPORTED, "moments need n_max <= 255 and angles <= 4096 (<= 1024 for ZM_F64)");
+    if (batch == 0) return ZM_OK;
+    if (batch > 65535) return fail(ZM_EINVAL, "batch must be <= 65535");
+    if (!d_ws) return fail(ZM_EINVAL, "null workspace");
+    const size_t need = workspace_bytes(p, batch);
+    if (ws_bytes < need) return fail(ZM_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    return ZM_OK;
+}
+
+static float* fmax_slot(zm_plan_t p, void* d_ws, int batch) {
+    return p->dtype == ZM_F16X2 ? (float*)((char*)d_ws + align256(spectrum_bytes(p, batch))) : nullptr;
+}
+
+static zm_status run_spectra(zm_plan_t p, const void* src, int batch, long long stride, void* d_ws,
+                             size_t ws_bytes, zm_stream_t stream, int from_polar) {
+    zm_status st = check_run(p, batch, d_ws, ws_bytes);
+    if (st != ZM_OK || batch == 0) return st;
+    if (!src) return fail(ZM_EINVAL, "null input pointer");
+    hipStream_t s = (hipStream_t)stream;
+    float* fmax = fmax_slot(p, d_ws, batch);
+    if (fmax) {
+        hipError_t e = launch_zero_u32((unsigned*)fmax, (size_t)batch, s);
+        if (e != hipSuccess) return hip_fail(e, "zero kernel launch");
+    }
+    hipError_t e = launch_polar_fft(p, src, stride, batch, d_ws, fmax, from_polar, s);
+    if (e != hipSuccess) return hip_fail(e, "resample+FFT kernel launch");
+    return ZM_OK;
+}
+
+zm_status zm_spectra(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_ws,
+                     size_t ws_bytes, zm_stream_t stream) {
+    if (p && batch > 1 && image_stride < (long long)p->H * p->W)
+        return fail(ZM_EINVAL, "image_stride must be >= H * W");
+    return run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0);
+}
+
+zm_status zm_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
+    zm_status st = check_run(p, batch, d_ws, ws_bytes);
+    if (st != ZM_OK || batch == 0) return st;
+    if (!d_Z) return fail(ZM_EINVAL, "null output pointer");
+    hipError_t e = launch_project(p, d_ws, fmax_slot(p, d_ws, batch), batch, d_Z, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
+    return ZM_OK;
+}
+
+zm_status zm_moments(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_Z, void* d_ws,
+                     size_t ws_bytes, zm_stream_t stream) {
+    if (batch > 0 && !d_Z) return fail(ZM_EINVAL, "null output pointer");
+    zm_status st = zm_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream);
+    if (st != ZM_OK) return st;
+    return zm_project(p, batch, d_Z, d_ws, ws_bytes, stream);
+}
+
+zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_Z, void* d_ws, size_t ws_bytes,
+                           zm_stream_t stream) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch > 0 && !d_Z) return fail(ZM_EINVAL, "null output pointer");
+    zm_status st = run_spectra(p, d_polar, batch, (long long)p->R * p->A, d_ws, ws_bytes, stream, 1);
+    if (st != ZM_OK) return st;
+    return zm_project(p, batch, d_Z, d_ws, ws_bytes, stream);
+}
+
+zm_status zm_destroy(zm_plan_t p) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    (void)hipSetDevice(p->device);
+    free_plan(p);
+    return ZM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,92 @@
+// Internal declarations shared by the libzm translation units (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "zm.h"
+
+namespace zm {
+
+// Error detail for zm_last_error (thread-local).
+void set_error(const std::string& msg);
+zm_status fail(zm_status s, const std::string& msg);
+zm_status hip_fail(hipError_t e, const char* what);
+
+#define ZM_HIP(call)                                     \
+    do {                                                 \
+        hipError_t e_ = (call);                          \
+        if (e_ != hipSuccess) return zm::hip_fail(e_, #call); \
+    } while (0)
+
+// Largest order the moment kernels serve (the pruned FFT keeps bins
+// 0..n_max inside one sub-transform of at most 256 points).
+constexpr int kMaxMomentOrder = 255;
+constexpr int kMaxTableOrder = 500;
+constexpr int kMaxAngles = 4096;
+constexpr int kMinAngles = 32;
+constexpr int kMaxRings = 4096;
+constexpr int kRingTile = 16;   // rings per resample+FFT workgroup
+constexpr int kRingPad = 32;    // rings padded to a multiple of this (projection K step)
+constexpr int kRowTile = 16;    // projection rows per MFMA tile (per m block)
+
+// Canonical position of (n, m) (n ascending, then m ascending, m = n mod 2 .. n step 2).
+__host__ __device__ inline int canon_index(int n, int m) {
+    int p = n >> 1;
+    int off = (n & 1) ? (p + 1) * (p + 1) : p * (p + 1);
+    return off + (m >> 1);
+}
+
+}  // namespace zm
+
+// One projection work item: the rows [row0, row0 + rows) of the m block.
+struct zm_item {
+    int m;
+    int row0;   // first row (n = m + 2 * row) inside the block
+    int rows;   // 16 or 32
+    int toff;   // first table row of the block in the operand table
+};
+
+struct zm_plan_s {
+    int n_max, H, W, D, R, A, Rp, M, num_moments;
+    int A2;         // pruned sub-transform length (16 * Q, >= n_max + 1)
+    int NK;         // DFT length of the radial-table relation
+    zm_dtype dtype;
+    int neumann;
+    zm_ring_rule rule;
+    int device;
+    double cx, cy, rpx;
+
+    std::vector<double> rho, w;          // ring nodes and weights (host)
+    std::vector<int> blk_rows;           // K_m per m
+    std::vector<int> blk_toff;           // first operand-table row of each m block
+    int table_rows;                      // operand-table rows incl. padding
+    std::vector<zm_item> items;          // projection work items
+
+    // device memory owned by the plan
+    double* d_spx = nullptr;             // rho_r * D/2 (pixels), R
+    double* d_trig = nullptr;            // cos/sin(2 pi a / A), [A][2]
+    void* d_tw = nullptr;                // FFT twiddles exp(-2 pi i j / A) as (cos, sin), [A][2]
+    double* d_table = nullptr;           // R_nm(rho_r), [num_moments][R], FP64 (eq. (7))
+    void* d_thi = nullptr;               // projection operand (or its hi part)
+    void* d_tlo = nullptr;               // lo part (split dtypes)
+    float* d_rowscale = nullptr;         // per operand row: factor undoing the F16 row scaling
+    zm_item* d_items = nullptr;
+    int* d_rowmap = nullptr;             // operand row -> canonical idx (-1 for padding)
+    size_t resident = 0;
+};
+
+namespace zm {
+// Kernels launchers (each returns hipSuccess or the launch error).
+hipError_t launch_zrp_table(const zm_plan_s* p, const double* d_rho, const double* d_ck, hipStream_t s);
+hipError_t launch_fold(const zm_plan_s* p, const double* d_w, hipStream_t s);
+hipError_t launch_polar_fft(const zm_plan_s* p, const void* img, long long stride, int batch, void* F,
+                            float* fmax, int from_polar, hipStream_t s);
+hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z,
+                          hipStream_t s);
+hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s);
+}  // namespace zm
