@@ -151,6 +151,47 @@ zm_status zm_project(zm_plan_t plan, int batch, void* d_Z, void* d_ws, size_t ws
 zm_status zm_moments_polar(zm_plan_t plan, const void* d_polar, int batch, void* d_Z, void* d_ws,
                            size_t ws_bytes, zm_stream_t stream);
 
+/* ---- Reconstruction (Sec. 2.2 eq. (9)), error (Sec. 2.4 eq. (13)), min-max ---- */
+
+typedef enum { ZM_RECON_POLAR = 0, ZM_RECON_CARTESIAN = 1 } zm_recon_kind;
+enum {
+    ZM_RECON_ONESIDED = 1, /* sum Re(Z_nm exp(j m theta)) R_nm over stored m >= 0 once (no conj terms, no eps) */
+    ZM_RECON_MINMAX = 2    /* CARTESIAN only: affine-map the result onto [min, max] of d_ref over the disk
+                              (Sec. 2.3 / Sec. 3 renormalisation, per frame = per band) */
+};
+
+/* Image series of eq. (9) from moments d_Z ([batch][num_moments][2], the
+ * plan's real type), FP64 accumulation, asynchronous:
+ *   ZM_RECON_POLAR     : d_out [batch][R][A], f~ at the plan's polar nodes
+ *                        (R_nm from the plan's eq. (7) table);
+ *   ZM_RECON_CARTESIAN : d_out [batch][H][W], f~ at pixel centres with
+ *                        rho <= 1, 0 outside (R_nm by the Jacobi recurrence).
+ * Z_{n,-m} = conj(Z_nm) supplies the m < 0 terms; for a Neumann plan the
+ * factor eps_m of eq. (14)-(15) is multiplied back, so both normalisations
+ * reconstruct the same image.  d_ref (frames, [batch][H][W]) is read only
+ * with ZM_RECON_MINMAX.  d_ws: zm_recon_workspace_size bytes (may be NULL
+ * without ZM_RECON_MINMAX).  Output/input real type: float, double for ZM_F64. */
+zm_status zm_reconstruct(zm_plan_t plan, const void* d_Z, int batch, void* d_out, int kind, int flags,
+                         const void* d_ref, void* d_ws, size_t ws_bytes, zm_stream_t stream);
+zm_status zm_recon_workspace_size(zm_plan_t plan, int batch, size_t* bytes);
+
+/* Reconstruction error over the disk (pixel centres with rho <= 1) between
+ * frames d_ref and reconstructions d_recon ([batch][H][W]).  host_out
+ * receives batch rows of 5 doubles: eq. (13) epsilon = SSE / (f_max^2 * count),
+ * eq. (10) epsilon_1 = SSE / sum f^2, SSE, f_max = max |f|, count.
+ * Deterministic (fixed reduction order).  Synchronises the stream. */
+zm_status zm_recon_error(zm_plan_t plan, const void* d_ref, const void* d_recon, int batch, double* host_out,
+                         void* d_ws, size_t ws_bytes, zm_stream_t stream);
+
+/* Embedding of Sec. 3: an N x N image is placed in a zero grid of size
+ * N + floor(N (sqrt 2 - 1)) + 20 at offset floor(N (sqrt 2 - 1) / 2) + 10 in
+ * both directions, so the whole image lies inside the inscribed disk.
+ * zm_pad_size returns size and offset (computed exactly in integers;
+ * N = 256 gives 382 and 63).  zm_embed copies a batch of n x n frames
+ * (float, or double if is_double) into size x size frames. */
+zm_status zm_pad_size(int n, int* size, int* offset);
+zm_status zm_embed(const void* d_src, int n, int batch, void* d_dst, int is_double, zm_stream_t stream);
+
 zm_status zm_destroy(zm_plan_t plan);
 
 const char* zm_status_str(zm_status s);

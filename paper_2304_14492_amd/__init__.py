@@ -63,6 +63,11 @@ _SIGS = {
     "zm_moments_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "zm_spectra": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _sz, _vp]),
     "zm_project": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "zm_reconstruct": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "zm_recon_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_sz)]),
+    "zm_recon_error": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _sz, _vp]),
+    "zm_pad_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "zm_embed": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp]),
     "zm_destroy": (ctypes.c_int, [_vp]),
     "zm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "zm_last_error": (ctypes.c_char_p, []),
@@ -91,6 +96,31 @@ def num_moments(n_max: int) -> int:
 
 def index(n: int, m: int) -> int:
     return _lib.zm_index(n, m)
+
+
+RECON_POLAR, RECON_CARTESIAN = 0, 1
+RECON_ONESIDED, RECON_MINMAX = 1, 2
+
+
+def pad_size(n: int):
+    """(size, offset) of the Sec. 3 embedding of an n x n image."""
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.zm_pad_size(n, ctypes.byref(a), ctypes.byref(b)), "zm_pad_size")
+    return a.value, b.value
+
+
+def embed(frames, stream=None):
+    """Embed [B, n, n] frames (float32/float64 CUDA) into [B, size, size] zero grids (Sec. 3)."""
+    import torch
+    B, n, n2 = frames.shape
+    if n != n2:
+        raise ValueError("embed expects square frames")
+    frames = frames.contiguous()
+    size, _ = pad_size(n)
+    out = torch.empty(B, size, size, dtype=frames.dtype, device=frames.device)
+    _check(_lib.zm_embed(_vp(frames.data_ptr()), n, B, _vp(out.data_ptr()), int(frames.dtype == torch.float64),
+                         _stream_handle(stream)), "zm_embed")
+    return out
 
 
 def exported_symbols():
@@ -230,6 +260,50 @@ class Plan:
                                      _vp(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)),
                "zm_moments_polar")
         return out[0] if squeeze else out
+
+
+def _recon_ws(plan, batch, device):
+    import torch
+    n = _sz()
+    _check(_lib.zm_recon_workspace_size(plan._h, batch, ctypes.byref(n)), "zm_recon_workspace_size")
+    return torch.empty(max(n.value, 1), dtype=torch.uint8, device=device)
+
+
+def reconstruct(plan, Z, kind="cartesian", one_sided=False, minmax_ref=None, stream=None):
+    """eq. (9) from moments Z [B, num_moments, 2] (plan's real dtype, CUDA).
+    kind "polar" -> [B, R, A]; "cartesian" -> [B, H, W] (0 outside the disk).
+    minmax_ref: frames [B, H, W] to renormalise onto (Cartesian only)."""
+    import torch
+    squeeze = Z.dim() == 2
+    if squeeze:
+        Z = Z.unsqueeze(0)
+    Z = Z.contiguous()
+    B = Z.shape[0]
+    k = RECON_POLAR if kind == "polar" else RECON_CARTESIAN
+    shape = (B, plan.rings, plan.angles) if k == RECON_POLAR else (B, plan.H, plan.W)
+    out = torch.empty(shape, dtype=plan._real_dtype(), device=Z.device)
+    flags = (RECON_ONESIDED if one_sided else 0) | (RECON_MINMAX if minmax_ref is not None else 0)
+    ws = _recon_ws(plan, B, Z.device)
+    ref = minmax_ref.contiguous() if minmax_ref is not None else None
+    _check(_lib.zm_reconstruct(plan._h, _vp(Z.data_ptr()), B, _vp(out.data_ptr()), k, flags,
+                               _vp(ref.data_ptr()) if ref is not None else None, _vp(ws.data_ptr()), ws.numel(),
+                               _stream_handle(stream)), "zm_reconstruct")
+    return out[0] if squeeze else out
+
+
+def recon_error(plan, ref, recon, stream=None):
+    """eq. (13) (and eq. (10)) per frame over the disk: list of dicts."""
+    import numpy as np
+    if ref.dim() == 2:
+        ref, recon = ref.unsqueeze(0), recon.unsqueeze(0)
+    ref, recon = ref.contiguous(), recon.contiguous()
+    B = ref.shape[0]
+    ws = _recon_ws(plan, B, ref.device)
+    out = np.empty((B, 5), dtype=np.float64)
+    _check(_lib.zm_recon_error(plan._h, _vp(ref.data_ptr()), _vp(recon.data_ptr()), B,
+                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _vp(ws.data_ptr()), ws.numel(),
+                               _stream_handle(stream)), "zm_recon_error")
+    return [dict(eps13=r[0], eps10=r[1], sse=r[2], fmax=r[3], count=int(r[4])) for r in out]
 
 
 def as_complex(Z):

@@ -484,6 +484,90 @@ zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_
     return zm_project(p, batch, d_Z, d_ws, ws_bytes, stream);
 }
 
+zm_status zm_recon_workspace_size(zm_plan_t p, int batch, size_t* bytes) {
+    if (!p || !bytes) return fail(ZM_EINVAL, "null plan or output");
+    if (batch < 0) return fail(ZM_EINVAL, "negative batch");
+    const size_t nblk = recon_reduce_blocks(p);
+    *bytes = align256((size_t)batch * nblk * 4 * sizeof(double)) + align256((size_t)batch * 5 * sizeof(double));
+    return ZM_OK;
+}
+
+zm_status zm_reconstruct(zm_plan_t p, const void* d_Z, int batch, void* d_out, int kind, int flags,
+                         const void* d_ref, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch < 0 || batch > 65535) return fail(ZM_EINVAL, "batch must be in [0, 65535]");
+    if (kind != ZM_RECON_POLAR && kind != ZM_RECON_CARTESIAN) return fail(ZM_EINVAL, "unknown reconstruction kind");
+    if (flags & ~(ZM_RECON_ONESIDED | ZM_RECON_MINMAX)) return fail(ZM_EINVAL, "unknown reconstruction flags");
+    if ((flags & ZM_RECON_MINMAX) && kind != ZM_RECON_CARTESIAN)
+        return fail(ZM_EINVAL, "ZM_RECON_MINMAX applies to Cartesian reconstructions");
+    if (batch == 0) return ZM_OK;
+    if (!d_Z || !d_out) return fail(ZM_EINVAL, "null device pointer");
+    hipStream_t s = (hipStream_t)stream;
+    const int one = (flags & ZM_RECON_ONESIDED) ? 1 : 0;
+    hipError_t e = kind == ZM_RECON_POLAR ? launch_recon_polar(p, d_Z, batch, d_out, one, s)
+                                          : launch_recon_cart(p, d_Z, batch, d_out, one, s);
+    if (e != hipSuccess) return hip_fail(e, "reconstruction kernel launch");
+    if (flags & ZM_RECON_MINMAX) {
+        size_t need = 0;
+        zm_recon_workspace_size(p, batch, &need);
+        if (!d_ref || !d_ws || ws_bytes < need)
+            return fail(ZM_EINVAL, "ZM_RECON_MINMAX needs d_ref and a workspace of zm_recon_workspace_size bytes");
+        double* part = (double*)d_ws;
+        double* mm = (double*)((char*)d_ws + align256((size_t)batch * recon_reduce_blocks(p) * 4 * sizeof(double)));
+        e = launch_minmax(p, d_ref, d_out, batch, part, mm, s);
+        if (e != hipSuccess) return hip_fail(e, "min-max kernel launch");
+    }
+    return ZM_OK;
+}
+
+zm_status zm_recon_error(zm_plan_t p, const void* d_ref, const void* d_recon, int batch, double* host_out,
+                         void* d_ws, size_t ws_bytes, zm_stream_t stream) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch < 0 || batch > 65535) return fail(ZM_EINVAL, "batch must be in [0, 65535]");
+    if (batch == 0) return ZM_OK;
+    size_t need = 0;
+    zm_recon_workspace_size(p, batch, &need);
+    if (!d_ref || !d_recon || !host_out || !d_ws || ws_bytes < need)
+        return fail(ZM_EINVAL, "null pointer or workspace smaller than zm_recon_workspace_size");
+    hipStream_t s = (hipStream_t)stream;
+    double* part = (double*)d_ws;
+    double* out = (double*)((char*)d_ws + align256((size_t)batch * recon_reduce_blocks(p) * 4 * sizeof(double)));
+    hipError_t e = launch_recon_error(p, d_ref, d_recon, batch, part, out, s);
+    if (e != hipSuccess) return hip_fail(e, "error kernel launch");
+    ZM_HIP(hipMemcpyAsync(host_out, out, (size_t)batch * 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    ZM_HIP(hipStreamSynchronize(s));
+    return ZM_OK;
+}
+
+static long isqrt_l(long v) {
+    long r = (long)std::sqrt((double)v);
+    while (r * r > v) --r;
+    while ((r + 1) * (r + 1) <= v) ++r;
+    return r;
+}
+
+zm_status zm_pad_size(int n, int* size, int* offset) {
+    if (n < 1 || n > 1000000 || !size || !offset) return fail(ZM_EINVAL, "n must be >= 1 and outputs non-null");
+    // floor(n (sqrt 2 - 1)) = floor(sqrt(2 n^2)) - n, and floor(x / 2) = floor(floor(x) / 2)
+    const long fl = isqrt_l(2L * n * n) - n;
+    *size = (int)(n + fl + 20);
+    *offset = (int)(fl / 2 + 10);
+    return ZM_OK;
+}
+
+zm_status zm_embed(const void* d_src, int n, int batch, void* d_dst, int is_double, zm_stream_t stream) {
+    int size = 0, off = 0;
+    zm_status st = zm_pad_size(n, &size, &off);
+    if (st != ZM_OK) return st;
+    if (batch < 0 || batch > 65535) return fail(ZM_EINVAL, "batch must be in [0, 65535]");
+    if (batch == 0) return ZM_OK;
+    if (!d_src || !d_dst) return fail(ZM_EINVAL, "null device pointer");
+    hipError_t e = launch_embed(d_src, n, n, (long long)n * n, d_dst, size, off, off, batch, is_double ? 1 : 0,
+                                (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
+    return ZM_OK;
+}
+
 zm_status zm_destroy(zm_plan_t p) {
     if (!p) return fail(ZM_EINVAL, "null plan");
     (void)hipSetDevice(p->device);

@@ -155,37 +155,56 @@ struct RealTraits<double> {
     static constexpr int kMaxA2 = 128;  // LDS bound of the FP64 variant
 };
 
-// Bilinear sample of the frame at pixel coordinates (x, y) (FP64).  CHECK
-// selects the path that treats taps outside the frame as 0 (tap indices are
-// clamped before the loads, so no load leaves the frame); without CHECK the
-// caller guarantees 0 <= x < W - 1 and 0 <= y < H - 1.
+// Bilinear sample of the frame from tap origin (j0, i0) and fractions
+// (fx, fy) in [0, 1].  CHECK selects the path that treats taps outside the
+// frame as 0 (tap indices are clamped before the loads, so no load leaves the
+// frame); without CHECK the caller guarantees 0 <= j0 <= W-2, 0 <= i0 <= H-2.
 template <typename Real, bool CHECK>
-__device__ __forceinline__ Real bilinear_at(const Real* __restrict__ img, int H, int W, double x, double y) {
-    const double xf = floor(x), yf = floor(y);
-    const int j0 = (int)xf, i0 = (int)yf;
-    const Real fx = (Real)(x - xf), fy = (Real)(y - yf);
+__device__ __forceinline__ Real bilinear_idx(const Real* __restrict__ img, int H, int W, int j0, int i0, Real fx,
+                                             Real fy) {
     Real v00, v01, v10, v11;
     if (CHECK) {
         const int ja = min(max(j0, 0), W - 1), jb = min(max(j0 + 1, 0), W - 1);
         const int ia = min(max(i0, 0), H - 1), ib = min(max(i0 + 1, 0), H - 1);
         const bool jin0 = (unsigned)j0 < (unsigned)W, jin1 = (unsigned)(j0 + 1) < (unsigned)W;
         const bool iin0 = (unsigned)i0 < (unsigned)H, iin1 = (unsigned)(i0 + 1) < (unsigned)H;
-        const Real t00 = img[ia * W + ja], t01 = img[ia * W + jb];
-        const Real t10 = img[ib * W + ja], t11 = img[ib * W + jb];
+        const Real t00 = img[(unsigned)(ia * W + ja)], t01 = img[(unsigned)(ia * W + jb)];
+        const Real t10 = img[(unsigned)(ib * W + ja)], t11 = img[(unsigned)(ib * W + jb)];
         v00 = (iin0 && jin0) ? t00 : (Real)0;
         v01 = (iin0 && jin1) ? t01 : (Real)0;
         v10 = (iin1 && jin0) ? t10 : (Real)0;
         v11 = (iin1 && jin1) ? t11 : (Real)0;
     } else {
-        const Real* p = img + (i0 * W + j0);
-        v00 = p[0];
-        v01 = p[1];
-        v10 = p[W];
-        v11 = p[W + 1];
+        // two rows of two adjacent taps: each row is one 8-byte load
+        const Real* r0p = img + (i0 * W + j0);
+        const Real* r1p = r0p + W;
+        v00 = r0p[0];
+        v01 = r0p[1];
+        v10 = r1p[0];
+        v11 = r1p[1];
     }
     const Real top = v00 + fx * (v01 - v00);
     const Real bot = v10 + fx * (v11 - v10);
     return top + fy * (bot - top);
+}
+
+// floor and fraction of a pixel coordinate
+template <typename Real>
+struct Coord {
+    int i;
+    Real f;
+};
+template <typename Real>
+__device__ __forceinline__ Coord<Real> split_coord(double v) {
+    const double fl = floor(v);
+    return Coord<Real>{(int)fl, (Real)(v - fl)};
+}
+// K - v for integer K, from the split of v: floor = K - floor(v) - 1 and
+// fraction 1 - frac(v) (a fraction of exactly 1 when v is an integer, which
+// bilinear interpolation treats identically to fraction 0 one tap further).
+template <typename Real>
+__device__ __forceinline__ Coord<Real> mirror_coord(Coord<Real> c, int K) {
+    return Coord<Real>{K - c.i - 1, (Real)1 - c.f};
 }
 
 template <int A>
@@ -281,6 +300,7 @@ __global__ __launch_bounds__(FftShape<A>::NTHR) __attribute__((amdgpu_waves_per_
 
     const Real* frame = src + (size_t)img * (size_t)src_stride;
     float vmax = 0.f;
+
     __syncthreads();
 
     for (int rd = 0; rd < ROUNDS; ++rd) {
@@ -314,21 +334,26 @@ __global__ __launch_bounds__(FftShape<A>::NTHR) __attribute__((amdgpu_waves_per_
                 const int a = (tid + NTHR * i) / S::RPR;  // base angle, < A / 4
                 const double c = trig[2 * a], sn = trig[2 * a + 1];
                 const double pc = sr * c, ps = sr * sn;
-                const double xs[4] = {cx + pc, cx - ps, cx - pc, cx + ps};
-                const double ys[4] = {cy - ps, cy - pc, cy + ps, cy + pc};
+                // the four quarter turns: x = cx + (pc, -ps, -pc, ps), y = cy - (ps, pc, -ps, -pc);
+                // with 2 cx = W - 1 and 2 cy = H - 1 the negated offsets are mirrors
+                const Coord<Real> xa = split_coord<Real>(cx + pc), xb2 = split_coord<Real>(cx + ps);
+                const Coord<Real> yb = split_coord<Real>(cy + ps), yd = split_coord<Real>(cy + pc);
+                const Coord<Real> xs[4] = {xa, mirror_coord(xb2, W - 1), mirror_coord(xa, W - 1), xb2};
+                const Coord<Real> ys[4] = {mirror_coord(yb, H - 1), mirror_coord(yd, H - 1), yb, yd};
                 Real val[4];
                 if (!check) {
                     // every ring of the round lies inside the safe radius; rings
                     // past R (partial last round) sample the centre and are zeroed
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const Real v = bilinear_at<Real, false>(frame, H, W, xs[u], ys[u]);
+                        const Real v = bilinear_idx<Real, false>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f);
                         val[u] = ring < R ? v : (Real)0;
                     }
                 } else {
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        val[u] = ring < R ? bilinear_at<Real, true>(frame, H, W, xs[u], ys[u]) : (Real)0;
+                        val[u] = ring < R ? bilinear_idx<Real, true>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f)
+                                          : (Real)0;
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u) xf[2 * (a + u * (A / 4))] = val[u];
@@ -392,11 +417,11 @@ __global__ __launch_bounds__(FftShape<A>::NTHR) __attribute__((amdgpu_waves_per_
             // ring a: (X[m] + conj X[A-m]) / 2 ; ring b: (X[m] - conj X[A-m]) / (2 i)
             const Real fax = (Real)0.5 * (pm.x + nm.x), fay = (Real)0.5 * (pm.y - nm.y);
             const Real fbx = (Real)0.5 * (pm.y + nm.y), fby = (Real)0.5 * (nm.x - pm.x);
+            vmax = fmaxf(vmax, fmaxf(fmaxf((float)fabs((double)fax), (float)fabs((double)fay)),
+                                     fmaxf((float)fabs((double)fbx), (float)fabs((double)fby))));
             Real* o = Fo + (size_t)m * 2 * zm::kRingTile;  // ri even: 2-element aligned
             *reinterpret_cast<Pair2<Real>*>(o) = Pair2<Real>{fax, fbx};
             *reinterpret_cast<Pair2<Real>*>(o + zm::kRingTile) = Pair2<Real>{fay, fby};
-            vmax = fmaxf(vmax, fmaxf(fmaxf((float)fabs((double)fax), (float)fabs((double)fay)),
-                                     fmaxf((float)fabs((double)fbx), (float)fabs((double)fby))));
         }
     }
     if (fmaxbuf != nullptr) {

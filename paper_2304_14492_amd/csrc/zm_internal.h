@@ -89,4 +89,13 @@ hipError_t launch_polar_fft(const zm_plan_s* p, const void* img, long long strid
 hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z,
                           hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s);
+hipError_t launch_recon_polar(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s);
+hipError_t launch_recon_cart(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s);
+size_t recon_reduce_blocks(const zm_plan_s* p);
+hipError_t launch_recon_error(const zm_plan_s* p, const void* f, const void* g, int batch, double* part,
+                              double* out, hipStream_t s);
+hipError_t launch_minmax(const zm_plan_s* p, const void* f, void* g, int batch, double* part, double* mm,
+                         hipStream_t s);
+hipError_t launch_embed(const void* src, int n_rows, int n_cols, long long src_stride, void* dst, int size, int off_r,
+                        int off_c, int batch, int is_double, hipStream_t s);
 }  // namespace zm
