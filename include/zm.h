@@ -151,6 +151,48 @@ zm_status zm_project(zm_plan_t plan, int batch, void* d_Z, void* d_ws, size_t ws
 zm_status zm_moments_polar(zm_plan_t plan, const void* d_polar, int batch, void* d_Z, void* d_ws,
                            size_t ws_bytes, zm_stream_t stream);
 
+/* ---- Batched persistent form: frames of different sizes and orders ---- */
+
+/* One frame of a mixed batch: its plan (FP32-family dtype, n_max <= 255,
+ * 512 <= angles <= 4096), the device frame (H x W float, row-major) and the
+ * device output ([num_moments][2] float).  Frames sharing a plan are
+ * projected together. */
+typedef struct {
+    zm_plan_t plan;
+    const void* d_image;
+    void* d_Z;
+} zm_job;
+
+typedef struct zm_batch_s* zm_batch_t; /* owns its queue, descriptors, spectra workspace and graph */
+
+enum {
+    ZM_BATCH_AUTOTUNE = 1, /* time candidate persistent grid sizes / item orders once (runs the batch on the
+                              given frames); the choice is cached per batch signature in-process and, if the
+                              environment variable ZM_TUNE_CACHE names a file, in that file */
+    ZM_BATCH_NO_GRAPH = 2  /* launch directly instead of replaying a captured HIP graph */
+};
+
+/* Build the work queue of eq. (1) for all jobs (stage 1: fused resample +
+ * ring FFT per (frame, ring tile); stage 2: radial projection per (plan
+ * group, block)), allocate its device memory, optionally autotune, and
+ * capture [counter reset + persistent kernel] in a HIP graph.  Synchronous.
+ * Each frame's moments are bit-identical to zm_moments on that frame alone. */
+zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out);
+/* Run the batch on `stream` (asynchronous; one graph launch). */
+zm_status zm_batch_run(zm_batch_t batch, zm_stream_t stream);
+/* Point the batch at new frames / outputs (same plans, same order); waits for
+ * the device to be idle first. */
+zm_status zm_batch_update(zm_batch_t batch, const zm_job* jobs, int njobs);
+/* Synchronise the device and report ZM_EDEVICE if a stage-2 item ever waited
+ * past its bound (a failed dependency; never expected). */
+zm_status zm_batch_check(zm_batch_t batch);
+/* Chosen persistent grid size, item order (0 = costliest tiles first, 1 = natural),
+ * queue length and device bytes owned by the batch (any pointer may be NULL). */
+zm_status zm_batch_config(zm_batch_t batch, int* grid, int* order, int* n_items, size_t* device_bytes);
+zm_status zm_batch_destroy(zm_batch_t batch);
+/* One-shot: create (no graph), run, synchronise, check, destroy. */
+zm_status zm_moments_batch(const zm_job* jobs, int njobs, zm_stream_t stream);
+
 /* ---- Reconstruction (Sec. 2.2 eq. (9)), error (Sec. 2.4 eq. (13)), min-max ---- */
 
 typedef enum { ZM_RECON_POLAR = 0, ZM_RECON_CARTESIAN = 1 } zm_recon_kind;

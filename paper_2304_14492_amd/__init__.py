@@ -47,6 +47,10 @@ class zm_plan_info_t(ctypes.Structure):
                 ("workspace_bytes_per_image", ctypes.c_size_t), ("workspace_bytes_fixed", ctypes.c_size_t)]
 
 
+class zm_job(ctypes.Structure):
+    _fields_ = [("plan", ctypes.c_void_p), ("d_image", ctypes.c_void_p), ("d_Z", ctypes.c_void_p)]
+
+
 _vp = ctypes.c_void_p
 _sz = ctypes.c_size_t
 _SIGS = {
@@ -68,6 +72,14 @@ _SIGS = {
     "zm_recon_error": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), _vp, _sz, _vp]),
     "zm_pad_size": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
     "zm_embed": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_int, _vp]),
+    "zm_batch_create": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, ctypes.c_int, ctypes.POINTER(_vp)]),
+    "zm_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "zm_batch_update": (ctypes.c_int, [_vp, ctypes.POINTER(zm_job), ctypes.c_int]),
+    "zm_batch_check": (ctypes.c_int, [_vp]),
+    "zm_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_sz)]),
+    "zm_batch_destroy": (ctypes.c_int, [_vp]),
+    "zm_moments_batch": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp]),
     "zm_destroy": (ctypes.c_int, [_vp]),
     "zm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "zm_last_error": (ctypes.c_char_p, []),
@@ -304,6 +316,81 @@ def recon_error(plan, ref, recon, stream=None):
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _vp(ws.data_ptr()), ws.numel(),
                                _stream_handle(stream)), "zm_recon_error")
     return [dict(eps13=r[0], eps10=r[1], sse=r[2], fmax=r[3], count=int(r[4])) for r in out]
+
+
+BATCH_AUTOTUNE, BATCH_NO_GRAPH = 1, 2
+
+
+def _jobs(plans, frames, outs):
+    n = len(plans)
+    if not (len(frames) == n and len(outs) == n):
+        raise ValueError("plans, frames and outputs must have the same length")
+    arr = (zm_job * n)()
+    for i, (p, f, z) in enumerate(zip(plans, frames, outs)):
+        if f.shape[-2:] != (p.H, p.W) or not f.is_contiguous() or z.shape[-2:] != (p.num_moments, 2):
+            raise ValueError(f"job {i}: frame or output shape does not match its plan")
+        arr[i].plan = p.handle
+        arr[i].d_image = f.data_ptr()
+        arr[i].d_Z = z.data_ptr()
+    return arr
+
+
+class Batch:
+    """Mixed batch (frames of different sizes / orders) in one persistent
+    launch, replayed from a captured HIP graph.  frames[i] is a [H, W] float32
+    CUDA tensor matching plans[i]; outs[i] is [num_moments, 2] float32."""
+
+    def __init__(self, plans, frames, outs=None, autotune=False, graph=True):
+        import torch
+        if outs is None:
+            outs = [torch.empty(p.num_moments, 2, dtype=torch.float32, device=f.device) for p, f in zip(plans, frames)]
+        self.plans, self.frames, self.outs = list(plans), list(frames), list(outs)
+        jobs = _jobs(self.plans, self.frames, self.outs)
+        flags = (BATCH_AUTOTUNE if autotune else 0) | (0 if graph else BATCH_NO_GRAPH)
+        h = _vp()
+        _check(_lib.zm_batch_create(jobs, len(jobs), flags, ctypes.byref(h)), "zm_batch_create")
+        self._h = h
+
+    def run(self, stream=None):
+        _check(_lib.zm_batch_run(self._h, _stream_handle(stream)), "zm_batch_run")
+        return self.outs
+
+    def update(self, frames, outs=None):
+        if outs is not None:
+            self.outs = list(outs)
+        self.frames = list(frames)
+        jobs = _jobs(self.plans, self.frames, self.outs)
+        _check(_lib.zm_batch_update(self._h, jobs, len(jobs)), "zm_batch_update")
+
+    def check(self):
+        _check(_lib.zm_batch_check(self._h), "zm_batch_check")
+
+    def config(self):
+        g, o, n, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), _sz()
+        _check(_lib.zm_batch_config(self._h, ctypes.byref(g), ctypes.byref(o), ctypes.byref(n), ctypes.byref(b)),
+               "zm_batch_config")
+        return dict(grid=g.value, order=o.value, n_items=n.value, device_bytes=b.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.zm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def moments_batch(plans, frames, outs=None, stream=None):
+    """One-shot mixed batch (no graph); returns the list of [num_moments, 2] outputs."""
+    import torch
+    if outs is None:
+        outs = [torch.empty(p.num_moments, 2, dtype=torch.float32, device=f.device) for p, f in zip(plans, frames)]
+    jobs = _jobs(plans, frames, outs)
+    _check(_lib.zm_moments_batch(jobs, len(jobs), _stream_handle(stream)), "zm_moments_batch")
+    return outs
 
 
 def as_complex(Z):

@@ -1,0 +1,630 @@
+// Batched persistent form: frames of different sizes and orders in one
+// launch.
+//
+// The host groups the jobs by plan and builds a device work queue:
+//   stage-1 items (frame, ring tile)      -> fused resample + ring FFT,
+//   stage-2 items (plan group, 8 blocks)  -> radial projection on MFMA.
+// One persistent kernel pops items with an atomic counter.  A finished
+// stage-1 tile releases its writes (device-scope fence) and bumps its group's
+// counter; a stage-2 item waits (acquire) until its group's counter reaches
+// the group's tile count.  Every stage-1 item is popped before any stage-2
+// item (queue order), and stage-1 items never wait, so every wait ends; the
+// wait is bounded anyway and reports an error flag if the bound trips.
+// Each item runs exactly the code of the standalone kernels, so a frame's
+// moments are bit-identical alone and in a batch.
+//
+// A batch object captures [counter reset kernel + persistent kernel] in a
+// HIP graph once and replays it; a small autotuner picks the persistent grid
+// size and the item order by timing candidates.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fft_body.h"
+#include "project_body.h"
+
+namespace {
+
+using namespace zmk;
+using zm::fail;
+using zm::hip_fail;
+
+constexpr int kBatchThreads = 512;
+constexpr int kAList[4] = {512, 1024, 2048, 4096};
+constexpr int kA2List[5] = {16, 32, 64, 128, 256};
+
+// variants served by the persistent kernel: FP32 transforms with A >= 512
+// (512-thread shape), LDS within the batch kernel's budget
+template <int A, int A2>
+constexpr bool batch_variant_ok() {
+    return A2 * 2 <= A && FftLds<float, A, A2>::bytes <= 90 * 1024;
+}
+
+template <int AI, int A2I>
+constexpr size_t lds_of() {
+    if constexpr (batch_variant_ok<kAList[AI], kA2List[A2I]>())
+        return FftLds<float, kAList[AI], kA2List[A2I]>::bytes;
+    else
+        return 0;
+}
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
+template <int AI>
+constexpr size_t lds_row() {
+    return cmax(cmax(cmax(lds_of<AI, 0>(), lds_of<AI, 1>()), cmax(lds_of<AI, 2>(), lds_of<AI, 3>())), lds_of<AI, 4>());
+}
+constexpr size_t kBatchLds = cmax(cmax(lds_row<0>(), lds_row<1>()), cmax(lds_row<2>(), lds_row<3>()));
+
+struct BatchJob {
+    FftArgs<float> fa;
+    int variant;  // AI * 5 + A2I
+    int group;
+};
+
+struct BatchGroup {
+    ProjArgs pa;
+    int dtype;
+    unsigned tiles_total;
+};
+
+struct BatchItem {
+    int kind;  // 0: stage-1 (job, tile), 1: stage-2 (group, block of 8 units)
+    int idx;
+    int sub;
+    int pad;
+};
+
+// LDS of the persistent kernel, shared by all item bodies.  Each variant
+// body is a separate (non-inlined) function so that it gets its own register
+// allocation; it addresses this array directly, so its LDS accesses stay
+// LDS instructions.
+__shared__ __attribute__((aligned(16))) char g_batch_smem[kBatchLds];
+
+template <int AI, int A2I>
+__device__ __attribute__((noinline)) void run_tile(const BatchJob* j, int tile) {
+    if constexpr (batch_variant_ok<kAList[AI], kA2List[A2I]>())
+        polar_fft_tile<float, kAList[AI], kA2List[A2I]>(j->fa, 0, tile, g_batch_smem);
+}
+
+template <int AI>
+__device__ __forceinline__ void run_tile_a2(const BatchJob* j, int a2i, int tile) {
+    switch (a2i) {
+        case 0: run_tile<AI, 0>(j, tile); break;
+        case 1: run_tile<AI, 1>(j, tile); break;
+        case 2: run_tile<AI, 2>(j, tile); break;
+        case 3: run_tile<AI, 3>(j, tile); break;
+        case 4: run_tile<AI, 4>(j, tile); break;
+        default: break;
+    }
+}
+
+template <int DT>
+__device__ __attribute__((noinline)) void run_proj(const BatchGroup* g, int unit, int lane) {
+    project_unit<DT>(g->pa, unit, lane);
+}
+
+__global__ void batch_reset_kernel(unsigned* p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// ctr[0] = queue head, ctr[1 + g] = finished tiles of group g,
+// ctr[1 + n_groups] = error flag (a wait that hit its bound)
+__global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchItem* __restrict__ items, int n_items,
+                                                              const BatchJob* __restrict__ jobs,
+                                                              const BatchGroup* __restrict__ groups, int n_groups,
+                                                              unsigned* ctr, unsigned spin_limit) {
+    __shared__ int cur;
+    const int tid = threadIdx.x;
+    for (;;) {
+        __syncthreads();  // previous item's LDS users are done; `cur` is free
+        if (tid == 0) cur = (int)atomicAdd(&ctr[0], 1u);
+        __syncthreads();
+        const int i = cur;
+        if (i >= n_items) return;
+        const BatchItem it = items[i];
+        if (it.kind == 0) {
+            const BatchJob* j = jobs + it.idx;
+            const int variant = j->variant;
+            const int ai = variant / 5, a2i = variant % 5;
+            switch (ai) {
+                case 0: run_tile_a2<0>(j, a2i, it.sub); break;
+                case 1: run_tile_a2<1>(j, a2i, it.sub); break;
+                case 2: run_tile_a2<2>(j, a2i, it.sub); break;
+                case 3: run_tile_a2<3>(j, a2i, it.sub); break;
+                default: break;
+            }
+            __threadfence();  // release this tile's spectra (device scope)
+            __syncthreads();
+            if (tid == 0) atomicAdd(&ctr[1 + j->group], 1u);
+        } else {
+            const BatchGroup* g = groups + it.idx;
+            const unsigned need = g->tiles_total;
+            if (tid == 0) {
+                unsigned spins = 0;
+                while (__hip_atomic_load(&ctr[1 + it.idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    __builtin_amdgcn_s_sleep(8);
+                    if (++spins > spin_limit) {
+                        atomicOr(&ctr[1 + n_groups], 1u);
+                        break;
+                    }
+                }
+            }
+            __syncthreads();
+            __threadfence();  // acquire the group's spectra
+            const int unit = it.sub * (kBatchThreads / 64) + (tid >> 6);
+            if (unit < g->pa.n_units) {
+                switch (g->dtype) {
+                    case ZM_F32: run_proj<ZM_F32>(g, unit, tid & 63); break;
+                    case ZM_BF16X2: run_proj<ZM_BF16X2>(g, unit, tid & 63); break;
+                    case ZM_F16X2: run_proj<ZM_F16X2>(g, unit, tid & 63); break;
+                    default: break;
+                }
+            }
+        }
+    }
+}
+
+int a_index(int A) {
+    for (int i = 0; i < 4; ++i)
+        if (kAList[i] == A) return i;
+    return -1;
+}
+int a2_index(int A2) {
+    for (int i = 0; i < 5; ++i)
+        if (kA2List[i] == A2) return i;
+    return -1;
+}
+
+template <int AI, int A2I>
+bool host_ok() {
+    return batch_variant_ok<kAList[AI], kA2List[A2I]>();
+}
+bool variant_ok(int ai, int a2i) {
+    static const bool tab[4][5] = {
+        {host_ok<0, 0>(), host_ok<0, 1>(), host_ok<0, 2>(), host_ok<0, 3>(), host_ok<0, 4>()},
+        {host_ok<1, 0>(), host_ok<1, 1>(), host_ok<1, 2>(), host_ok<1, 3>(), host_ok<1, 4>()},
+        {host_ok<2, 0>(), host_ok<2, 1>(), host_ok<2, 2>(), host_ok<2, 3>(), host_ok<2, 4>()},
+        {host_ok<3, 0>(), host_ok<3, 1>(), host_ok<3, 2>(), host_ok<3, 3>(), host_ok<3, 4>()}};
+    return ai >= 0 && a2i >= 0 && tab[ai][a2i];
+}
+int pairs_of(int A) { return A == 512 ? 16 : 8; }  // FftShape<float, A>::PAIRS for A >= 512
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct zm_batch_s {
+    int device = 0;
+    int njobs = 0, ngroups = 0;
+    std::vector<zm_plan_t> plans;          // per job
+    std::vector<int> job_group, job_slot;  // group and position in the group
+    std::vector<BatchJob> hjobs;
+    std::vector<BatchGroup> hgroups;
+    std::vector<BatchItem> stage1, stage2;  // natural order
+    std::vector<std::vector<void*>> zptrs;  // per group
+    int n_items = 0;
+    int grid = 0;
+    int order = 0;  // 0: cost-descending stage 1, 1: natural
+    // device memory
+    char* d_mem = nullptr;
+    size_t d_bytes = 0;
+    BatchItem* d_items = nullptr;
+    BatchJob* d_jobs = nullptr;
+    BatchGroup* d_groups = nullptr;
+    void** d_zptrs = nullptr;
+    unsigned* d_zero = nullptr;  // counters + F16 max slots (cleared before every run)
+    int n_zero = 0;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned spin_limit = 1u << 24;
+};
+
+namespace {
+
+zm_status upload(zm_batch_s* b) {
+    std::vector<BatchItem> items;
+    std::vector<BatchItem> s1 = b->stage1;
+    if (b->order == 0) {
+        std::stable_sort(s1.begin(), s1.end(), [&](const BatchItem& x, const BatchItem& y) {
+            const zm_plan_s* px = b->plans[x.idx];
+            const zm_plan_s* py = b->plans[y.idx];
+            return (long)px->A * pairs_of(px->A) > (long)py->A * pairs_of(py->A);
+        });
+    }
+    items.insert(items.end(), s1.begin(), s1.end());
+    items.insert(items.end(), b->stage2.begin(), b->stage2.end());
+    b->n_items = (int)items.size();
+    ZM_HIP(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
+    ZM_HIP(hipMemcpy(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice));
+    ZM_HIP(hipMemcpy(b->d_groups, b->hgroups.data(), b->hgroups.size() * sizeof(BatchGroup), hipMemcpyHostToDevice));
+    std::vector<void*> flat;
+    for (auto& v : b->zptrs) flat.insert(flat.end(), v.begin(), v.end());
+    ZM_HIP(hipMemcpy(b->d_zptrs, flat.data(), flat.size() * sizeof(void*), hipMemcpyHostToDevice));
+    return ZM_OK;
+}
+
+hipError_t enqueue(zm_batch_s* b, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((b->n_zero + 255) / 256), dim3(256), 0, s, b->d_zero, b->n_zero);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_kernel, dim3(b->grid), dim3(kBatchThreads), 0, s, b->d_items, b->n_items, b->d_jobs,
+                       b->d_groups, b->ngroups, b->d_zero, b->spin_limit);
+    return hipGetLastError();
+}
+
+zm_status capture(zm_batch_s* b) {
+    if (b->exec) {
+        (void)hipGraphExecDestroy(b->exec);
+        b->exec = nullptr;
+    }
+    if (b->graph) {
+        (void)hipGraphDestroy(b->graph);
+        b->graph = nullptr;
+    }
+    ZM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue(b, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(b->stream, &g);
+    if (e != hipSuccess) return hip_fail(e, "batch launch capture");
+    if (e2 != hipSuccess) return hip_fail(e2, "hipStreamEndCapture");
+    b->graph = g;
+    ZM_HIP(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+    return ZM_OK;
+}
+
+std::string signature(const zm_batch_s* b) {
+    hipDeviceProp_t prop;
+    std::string sig;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess) sig = prop.gcnArchName;
+    std::vector<std::string> parts;
+    for (int i = 0; i < b->njobs; ++i) {
+        const zm_plan_s* p = b->plans[i];
+        char buf[96];
+        std::snprintf(buf, sizeof buf, "%dx%d:n%d:r%d:a%d:t%d", p->H, p->W, p->n_max, p->R, p->A, (int)p->dtype);
+        parts.push_back(buf);
+    }
+    std::sort(parts.begin(), parts.end());
+    for (auto& q : parts) sig += "|" + q;
+    return sig;
+}
+
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tune;  // signature -> (grid, order)
+bool g_tune_loaded = false;
+
+void tune_cache_load() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("ZM_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char line[8192];
+    while (std::fgets(line, sizeof line, f)) {
+        // one entry per line: <grid> <order> <signature>
+        int grid = 0, order = 0, n = 0;
+        if (std::sscanf(line, "%d %d %n", &grid, &order, &n) == 2 && grid > 0) {
+            std::string sig(line + n);
+            while (!sig.empty() && (sig.back() == '\n' || sig.back() == '\r')) sig.pop_back();
+            g_tune[sig] = {grid, order};
+        }
+    }
+    std::fclose(f);
+}
+
+void tune_cache_store(const std::string& sig, int grid, int order) {
+    g_tune[sig] = {grid, order};
+    const char* path = std::getenv("ZM_TUNE_CACHE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%d %d %s\n", grid, order, sig.c_str());
+    std::fclose(f);
+}
+
+zm_status check_error_flag(zm_batch_s* b) {
+    unsigned flag = 0;
+    ZM_HIP(hipMemcpy(&flag, b->d_zero + 1 + b->ngroups, sizeof(unsigned), hipMemcpyDeviceToHost));
+    if (flag) return fail(ZM_EDEVICE, "batch kernel: a projection item waited past its bound");
+    return ZM_OK;
+}
+
+zm_status autotune(zm_batch_s* b, int cus) {
+    const std::string sig = signature(b);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache_load();
+    auto it = g_tune.find(sig);
+    if (it != g_tune.end()) {
+        b->grid = it->second.first;
+        b->order = it->second.second;
+        return upload(b);
+    }
+    hipEvent_t e0, e1;
+    ZM_HIP(hipEventCreate(&e0));
+    ZM_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    int bg = cus, bo = 0;
+    const int grids[3] = {cus, 2 * cus, 4 * cus};
+    for (int order = 0; order < 2; ++order) {
+        b->order = order;
+        zm_status st = upload(b);
+        if (st != ZM_OK) return st;
+        for (int gi = 0; gi < 3; ++gi) {
+            b->grid = grids[gi];
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                ZM_HIP(hipEventRecord(e0, b->stream));
+                hipError_t e = enqueue(b, b->stream);
+                if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+                ZM_HIP(hipEventRecord(e1, b->stream));
+                ZM_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                ZM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ms_best = std::min(ms_best, ms);
+            }
+            if (ms_best < best) {
+                best = ms_best;
+                bg = grids[gi];
+                bo = order;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    zm_status st = check_error_flag(b);
+    if (st != ZM_OK) return st;
+    b->grid = bg;
+    b->order = bo;
+    tune_cache_store(sig, bg, bo);
+    return upload(b);
+}
+
+void destroy_batch(zm_batch_s* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->stream) (void)hipStreamDestroy(b->stream);
+    if (b->d_mem) (void)hipFree(b->d_mem);
+    delete b;
+}
+
+zm_status fill_pointers(zm_batch_s* b, const zm_job* jobs) {
+    for (int i = 0; i < b->njobs; ++i) {
+        if (!jobs[i].d_image || !jobs[i].d_Z) return fail(ZM_EINVAL, "job with a null frame or output pointer");
+        b->hjobs[i].fa.src = (const float*)jobs[i].d_image;
+        b->zptrs[b->job_group[i]][b->job_slot[i]] = jobs[i].d_Z;
+    }
+    return ZM_OK;
+}
+
+}  // namespace
+
+using namespace zm;
+
+extern "C" {
+
+zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out) {
+    if (!jobs || !out || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list and an output pointer");
+    *out = nullptr;
+    if (flags & ~(ZM_BATCH_AUTOTUNE | ZM_BATCH_NO_GRAPH)) return fail(ZM_EINVAL, "unknown batch flags");
+    zm_batch_s* b = new zm_batch_s();
+    b->njobs = njobs;
+    b->device = jobs[0].plan ? jobs[0].plan->device : 0;
+    std::map<zm_plan_t, int> gid;
+    std::vector<std::vector<int>> members;
+    for (int i = 0; i < njobs; ++i) {
+        zm_plan_t p = jobs[i].plan;
+        if (!p) {
+            destroy_batch(b);
+            return fail(ZM_EINVAL, "job with a null plan");
+        }
+        if (p->device != b->device) {
+            destroy_batch(b);
+            return fail(ZM_EINVAL, "all plans of a batch must be on one device");
+        }
+        if (p->dtype == ZM_F64 || p->n_max > kMaxMomentOrder || !variant_ok(a_index(p->A), a2_index(p->A2))) {
+            destroy_batch(b);
+            return fail(ZM_EUNSUPPORTED,
+                        "batch jobs need an FP32-family dtype, n_max <= 255 and 512 <= angles <= 4096");
+        }
+        if (!gid.count(p)) {
+            gid[p] = (int)members.size();
+            members.emplace_back();
+        }
+        b->plans.push_back(p);
+        b->job_group.push_back(gid[p]);
+        b->job_slot.push_back((int)members[gid[p]].size());
+        members[gid[p]].push_back(i);
+    }
+    b->ngroups = (int)members.size();
+    ZM_HIP(hipSetDevice(b->device));
+    // workspace layout: per group [F of its frames][F16 max slots]; counters
+    std::vector<size_t> foff(b->ngroups);
+    size_t fbytes = 0;
+    for (int g = 0; g < b->ngroups; ++g) {
+        const zm_plan_s* p = b->plans[members[g][0]];
+        foff[g] = fbytes;
+        fbytes += align256((size_t)members[g].size() * (size_t)(p->n_max + 1) * 2 * p->Rp * sizeof(float));
+    }
+    b->n_zero = 1 + b->ngroups + 1 + njobs;  // head, group counters, error flag, F16 max per frame
+    size_t n_items_max = 0;
+    for (int i = 0; i < njobs; ++i) n_items_max += (size_t)b->plans[i]->Rp / (2 * pairs_of(b->plans[i]->A));
+    for (int g = 0; g < b->ngroups; ++g) {
+        const zm_plan_s* p = b->plans[members[g][0]];
+        const size_t units = p->items.size() * ((2 * members[g].size() + 31) / 32);
+        n_items_max += (units + 7) / 8;
+    }
+    const size_t o_items = align256(fbytes);
+    const size_t o_jobs = o_items + align256(n_items_max * sizeof(BatchItem));
+    const size_t o_groups = o_jobs + align256((size_t)njobs * sizeof(BatchJob));
+    const size_t o_zptr = o_groups + align256((size_t)b->ngroups * sizeof(BatchGroup));
+    const size_t o_zero = o_zptr + align256((size_t)njobs * sizeof(void*));
+    b->d_bytes = o_zero + align256((size_t)b->n_zero * sizeof(unsigned));
+    hipError_t e = hipMalloc((void**)&b->d_mem, b->d_bytes);
+    if (e != hipSuccess) {
+        destroy_batch(b);
+        return hip_fail(e, "hipMalloc (batch)");
+    }
+    b->d_items = (BatchItem*)(b->d_mem + o_items);
+    b->d_jobs = (BatchJob*)(b->d_mem + o_jobs);
+    b->d_groups = (BatchGroup*)(b->d_mem + o_groups);
+    b->d_zptrs = (void**)(b->d_mem + o_zptr);
+    b->d_zero = (unsigned*)(b->d_mem + o_zero);
+
+    b->hjobs.resize(njobs);
+    b->zptrs.resize(b->ngroups);
+    size_t zbase = 0;
+    std::vector<size_t> zoff(b->ngroups);
+    for (int g = 0; g < b->ngroups; ++g) {
+        b->zptrs[g].assign(members[g].size(), nullptr);
+        zoff[g] = zbase;
+        zbase += members[g].size();
+    }
+    for (int i = 0; i < njobs; ++i) {
+        const zm_plan_s* p = b->plans[i];
+        const int g = b->job_group[i], k = b->job_slot[i];
+        BatchJob& j = b->hjobs[i];
+        j.fa.src = nullptr;
+        j.fa.src_stride = (long long)p->H * p->W;
+        j.fa.H = p->H;
+        j.fa.W = p->W;
+        j.fa.cx = p->cx;
+        j.fa.cy = p->cy;
+        j.fa.safe_s = std::min(p->cx, p->cy) - 1e-6;
+        j.fa.R = p->R;
+        j.fa.Rp = p->Rp;
+        j.fa.M = p->n_max + 1;
+        j.fa.from_polar = 0;
+        j.fa.spx = p->d_spx;
+        j.fa.trig = p->d_trig;
+        j.fa.tw = (const float*)p->d_tw;
+        j.fa.F = (float*)(b->d_mem + foff[g]) + (size_t)k * (p->n_max + 1) * 2 * p->Rp;
+        // F16 max slots: contiguous per group, after head, counters and flag
+        j.fa.fmaxbuf = p->dtype == ZM_F16X2 ? (float*)(b->d_zero + 2 + b->ngroups + zoff[g] + k) : nullptr;
+        j.variant = a_index(p->A) * 5 + a2_index(p->A2);
+        j.group = g;
+        const int tiles = p->Rp / (2 * pairs_of(p->A));
+        for (int t = 0; t < tiles; ++t) b->stage1.push_back(BatchItem{0, i, t, 0});
+    }
+    b->hgroups.resize(b->ngroups);
+    for (int g = 0; g < b->ngroups; ++g) {
+        const zm_plan_s* p = b->plans[members[g][0]];
+        const int n = (int)members[g].size();
+        BatchGroup& G = b->hgroups[g];
+        G.pa.items = p->d_items;
+        G.pa.ncb = (2 * n + 31) / 32;
+        G.pa.n_units = (int)p->items.size() * G.pa.ncb;
+        G.pa.thi = p->d_thi;
+        G.pa.tlo = p->d_tlo;
+        G.pa.rowscale = p->d_rowscale;
+        G.pa.F = b->d_mem + foff[g];
+        G.pa.fmaxbuf = p->dtype == ZM_F16X2 ? (const float*)(b->d_zero + 2 + b->ngroups + zoff[g]) : nullptr;
+        G.pa.B = n;
+        G.pa.M = p->n_max + 1;
+        G.pa.Rp = p->Rp;
+        G.pa.Mtot = p->num_moments;
+        G.pa.Z = nullptr;
+        G.pa.Zptrs = b->d_zptrs + zoff[g];
+        G.dtype = (int)p->dtype;
+        G.tiles_total = (unsigned)(n * (p->Rp / (2 * pairs_of(p->A))));
+        const int blocks = (G.pa.n_units + 7) / 8;
+        for (int k = 0; k < blocks; ++k) b->stage2.push_back(BatchItem{1, g, k, 0});
+    }
+    zm_status st = fill_pointers(b, jobs);
+    if (st != ZM_OK) {
+        destroy_batch(b);
+        return st;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, b->device);
+    const int cus = (e == hipSuccess && prop.multiProcessorCount > 0) ? prop.multiProcessorCount : 256;
+    b->grid = 2 * cus;
+    b->order = 0;
+    e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        destroy_batch(b);
+        return hip_fail(e, "hipStreamCreate");
+    }
+    st = upload(b);
+    if (st == ZM_OK && (flags & ZM_BATCH_AUTOTUNE)) st = autotune(b, cus);
+    if (st == ZM_OK && !(flags & ZM_BATCH_NO_GRAPH)) st = capture(b);
+    if (st != ZM_OK) {
+        destroy_batch(b);
+        return st;
+    }
+    *out = b;
+    return ZM_OK;
+}
+
+zm_status zm_batch_update(zm_batch_t b, const zm_job* jobs, int njobs) {
+    if (!b || !jobs) return fail(ZM_EINVAL, "null batch or jobs");
+    if (njobs != b->njobs) return fail(ZM_EINVAL, "job count differs from the batch");
+    for (int i = 0; i < njobs; ++i)
+        if (jobs[i].plan != b->plans[i]) return fail(ZM_EINVAL, "jobs must keep their plans and order");
+    zm_status st = fill_pointers(b, jobs);
+    if (st != ZM_OK) return st;
+    ZM_HIP(hipSetDevice(b->device));
+    ZM_HIP(hipDeviceSynchronize());  // descriptors may be in use by a running replay
+    return upload(b);
+}
+
+zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
+    if (!b) return fail(ZM_EINVAL, "null batch");
+    ZM_HIP(hipSetDevice(b->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) {
+        ZM_HIP(hipGraphLaunch(b->exec, s));
+        return ZM_OK;
+    }
+    hipError_t e = enqueue(b, s);
+    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    return ZM_OK;
+}
+
+zm_status zm_batch_check(zm_batch_t b) {
+    if (!b) return fail(ZM_EINVAL, "null batch");
+    ZM_HIP(hipSetDevice(b->device));
+    ZM_HIP(hipDeviceSynchronize());
+    return check_error_flag(b);
+}
+
+zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* n_items, size_t* device_bytes) {
+    if (!b) return fail(ZM_EINVAL, "null batch");
+    if (grid) *grid = b->grid;
+    if (order) *order = b->order;
+    if (n_items) *n_items = b->n_items;
+    if (device_bytes) *device_bytes = b->d_bytes;
+    return ZM_OK;
+}
+
+zm_status zm_batch_destroy(zm_batch_t b) {
+    if (!b) return fail(ZM_EINVAL, "null batch");
+    (void)hipSetDevice(b->device);
+    (void)hipDeviceSynchronize();
+    destroy_batch(b);
+    return ZM_OK;
+}
+
+zm_status zm_moments_batch(const zm_job* jobs, int njobs, zm_stream_t stream) {
+    zm_batch_t b = nullptr;
+    zm_status st = zm_batch_create(jobs, njobs, ZM_BATCH_NO_GRAPH, &b);
+    if (st != ZM_OK) return st;
+    st = zm_batch_run(b, stream);
+    if (st == ZM_OK) {
+        hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+        if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (st == ZM_OK) st = check_error_flag(b);
+    destroy_batch(b);
+    return st;
+}
+
+}  // extern "C"

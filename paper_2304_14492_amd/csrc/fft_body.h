@@ -1,0 +1,459 @@
+// Device bodies of the fused resample + angular FFT (see polar_fft.hip for
+// the method); shared by the standalone kernels and the persistent batch
+// kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "zm_internal.h"
+
+namespace zmk {
+
+template <typename Real>
+struct cplx {
+    Real x, y;
+};
+
+template <typename Real>
+__device__ __forceinline__ cplx<Real> operator+(cplx<Real> a, cplx<Real> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename Real>
+__device__ __forceinline__ cplx<Real> operator-(cplx<Real> a, cplx<Real> b) { return {a.x - b.x, a.y - b.y}; }
+// z * exp(-i t) with (c, s) = (cos t, sin t)
+template <typename Real>
+__device__ __forceinline__ cplx<Real> mulw(cplx<Real> z, Real c, Real s) {
+    return {z.x * c + z.y * s, z.y * c - z.x * s};
+}
+// z * (-i)
+template <typename Real>
+__device__ __forceinline__ cplx<Real> mul_mi(cplx<Real> z) { return {z.y, -z.x}; }
+
+// cos / sin of 2 pi p / 16 for the radix-16 internal twiddles
+constexpr double kC1 = 0.92387953251128675613;  // cos(pi/8)
+constexpr double kS1 = 0.38268343236508977173;  // sin(pi/8)
+constexpr double kR2 = 0.70710678118654752440;  // cos(pi/4)
+
+template <typename Real>
+__device__ __forceinline__ void dft4(cplx<Real>& a, cplx<Real>& b, cplx<Real>& c, cplx<Real>& d) {
+    cplx<Real> s0 = a + c, d0 = a - c, s1 = b + d, d1 = mul_mi(b - d);
+    a = s0 + s1;
+    c = s0 - s1;
+    b = d0 + d1;
+    d = d0 - d1;
+}
+
+// In-place length-N forward DFT (exp(-2 pi i j k / N)), natural order in and out.
+template <typename Real, int N>
+struct SmallDft;
+
+template <typename Real>
+struct SmallDft<Real, 1> {
+    __device__ __forceinline__ static void run(cplx<Real>*) {}
+};
+template <typename Real>
+struct SmallDft<Real, 2> {
+    __device__ __forceinline__ static void run(cplx<Real>* z) {
+        cplx<Real> t = z[0];
+        z[0] = t + z[1];
+        z[1] = t - z[1];
+    }
+};
+template <typename Real>
+struct SmallDft<Real, 4> {
+    __device__ __forceinline__ static void run(cplx<Real>* z) { dft4(z[0], z[1], z[2], z[3]); }
+};
+template <typename Real>
+struct SmallDft<Real, 8> {
+    // j = j1 + 2 j2, k = k1 + 4 k2: length-4 DFTs over j2, twiddle W8^(j1 k1), length-2 over j1
+    __device__ __forceinline__ static void run(cplx<Real>* z) {
+        cplx<Real> u0[4] = {z[0], z[2], z[4], z[6]};
+        cplx<Real> u1[4] = {z[1], z[3], z[5], z[7]};
+        dft4(u0[0], u0[1], u0[2], u0[3]);
+        dft4(u1[0], u1[1], u1[2], u1[3]);
+        const Real r2 = (Real)kR2;
+        u1[1] = mulw(u1[1], r2, r2);
+        u1[2] = mul_mi(u1[2]);
+        u1[3] = mulw(u1[3], -r2, r2);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            z[k1] = u0[k1] + u1[k1];
+            z[k1 + 4] = u0[k1] - u1[k1];
+        }
+    }
+};
+template <typename Real>
+struct SmallDft<Real, 16> {
+    // j = j1 + 4 j2, k = k1 + 4 k2: length-4 DFTs over j2, twiddle W16^(j1 k1), length-4 over j1
+    __device__ __forceinline__ static void run(cplx<Real>* z) {
+#pragma unroll
+        for (int j1 = 0; j1 < 4; ++j1) dft4(z[j1], z[j1 + 4], z[j1 + 8], z[j1 + 12]);
+        finish(z);
+    }
+    // second half: z[j1 + 4 k1] = U[j1][k1] on entry, natural order on exit
+    __device__ __forceinline__ static void finish(cplx<Real>* z) {
+        const Real c1 = (Real)kC1, s1 = (Real)kS1, r2 = (Real)kR2;
+        z[5] = mulw(z[5], c1, s1);      // W16^1
+        z[9] = mulw(z[9], r2, r2);      // W16^2
+        z[13] = mulw(z[13], s1, c1);    // W16^3
+        z[6] = mulw(z[6], r2, r2);      // W16^2
+        z[10] = mul_mi(z[10]);          // W16^4
+        z[14] = mulw(z[14], -r2, r2);   // W16^6
+        z[7] = mulw(z[7], s1, c1);      // W16^3
+        z[11] = mulw(z[11], -r2, r2);   // W16^6
+        z[15] = mulw(z[15], -c1, -s1);  // W16^9
+        cplx<Real> out[16];
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            // U[j1][k1] sits at z[j1 + 4 k1]; the length-4 DFT over j1 gives X[k1 + 4 k2]
+            cplx<Real> a = z[4 * k1 + 0], b = z[4 * k1 + 1], c = z[4 * k1 + 2], d = z[4 * k1 + 3];
+            dft4(a, b, c, d);
+            out[k1 + 0] = a;
+            out[k1 + 4] = b;
+            out[k1 + 8] = c;
+            out[k1 + 12] = d;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) z[i] = out[i];
+    }
+};
+
+template <typename Real>
+struct alignas(2 * sizeof(Real)) Pair2 {
+    Real a, b;
+};
+
+template <typename Real>
+struct RealTraits;
+template <>
+struct RealTraits<float> {
+    static constexpr int kMaxA = 4096;
+    static constexpr int kMaxA2 = 256;
+};
+template <>
+struct RealTraits<double> {
+    static constexpr int kMaxA = 1024;
+    static constexpr int kMaxA2 = 128;  // LDS bound of the FP64 variant
+};
+
+// Bilinear sample of the frame from tap origin (j0, i0) and fractions
+// (fx, fy) in [0, 1].  CHECK selects the path that treats taps outside the
+// frame as 0 (tap indices are clamped before the loads, so no load leaves the
+// frame); without CHECK the caller guarantees 0 <= j0 <= W-2, 0 <= i0 <= H-2.
+template <typename Real, bool CHECK>
+__device__ __forceinline__ Real bilinear_idx(const Real* __restrict__ img, int H, int W, int j0, int i0, Real fx,
+                                             Real fy) {
+    Real v00, v01, v10, v11;
+    if (CHECK) {
+        const int ja = min(max(j0, 0), W - 1), jb = min(max(j0 + 1, 0), W - 1);
+        const int ia = min(max(i0, 0), H - 1), ib = min(max(i0 + 1, 0), H - 1);
+        const bool jin0 = (unsigned)j0 < (unsigned)W, jin1 = (unsigned)(j0 + 1) < (unsigned)W;
+        const bool iin0 = (unsigned)i0 < (unsigned)H, iin1 = (unsigned)(i0 + 1) < (unsigned)H;
+        const Real t00 = img[(unsigned)(ia * W + ja)], t01 = img[(unsigned)(ia * W + jb)];
+        const Real t10 = img[(unsigned)(ib * W + ja)], t11 = img[(unsigned)(ib * W + jb)];
+        v00 = (iin0 && jin0) ? t00 : (Real)0;
+        v01 = (iin0 && jin1) ? t01 : (Real)0;
+        v10 = (iin1 && jin0) ? t10 : (Real)0;
+        v11 = (iin1 && jin1) ? t11 : (Real)0;
+    } else {
+        // two rows of two adjacent taps: each row is one 8-byte load
+        const Real* r0p = img + (i0 * W + j0);
+        const Real* r1p = r0p + W;
+        v00 = r0p[0];
+        v01 = r0p[1];
+        v10 = r1p[0];
+        v11 = r1p[1];
+    }
+    const Real top = v00 + fx * (v01 - v00);
+    const Real bot = v10 + fx * (v11 - v10);
+    return top + fy * (bot - top);
+}
+
+// floor and fraction of a pixel coordinate
+template <typename Real>
+struct Coord {
+    int i;
+    Real f;
+};
+template <typename Real>
+__device__ __forceinline__ Coord<Real> split_coord(double v) {
+    const double fl = floor(v);
+    return Coord<Real>{(int)fl, (Real)(v - fl)};
+}
+// K - v for integer K, from the split of v: floor = K - floor(v) - 1 and
+// fraction 1 - frac(v) (a fraction of exactly 1 when v is an integer, which
+// bilinear interpolation treats identically to fraction 0 one tap further).
+template <typename Real>
+__device__ __forceinline__ Coord<Real> mirror_coord(Coord<Real> c, int K) {
+    return Coord<Real>{K - c.i - 1, (Real)1 - c.f};
+}
+
+template <typename Real>
+struct FftArgs {
+    const Real* src;       // frames (or polar images with from_polar)
+    long long src_stride;  // elements between frames
+    int H, W;
+    double cx, cy, safe_s;  // disk centre; rings with s_r < safe_s never touch the frame edge
+    int R, Rp, M, from_polar;
+    const double* spx;     // ring radius in pixels, R
+    const double* trig;    // (cos, sin)(2 pi a / A), FP64
+    const Real* tw;        // (cos, sin)(2 pi a / A), compute precision
+    Real* F;               // spectra, ring-tile-blocked layout
+    float* fmaxbuf;        // per-frame max |F| (FP16 split) or null
+};
+
+template <typename Real, int A>
+struct FftShape {
+    static constexpr int NT = A / 16;  // threads per transform
+    // transforms (ring pairs) in flight: 512 threads per workgroup for FP32
+    // with A >= 512 (two workgroups per CU at A = 4096), at most 8 otherwise
+    static constexpr bool kWide = A >= 512 && sizeof(Real) == 4;
+    static constexpr int P = kWide ? 512 / NT : ((512 / NT) > 8 ? 8 : (512 / NT));
+    static constexpr int NTHR = NT * P;               // workgroup size
+    static constexpr int PAIRS = P > 8 ? P : 8;       // ring pairs per workgroup (16 or 32 rings)
+    static constexpr int ROUNDS = PAIRS / P;
+    static constexpr int RPR = 2 * P;                 // rings gathered per round
+};
+
+// LDS row padding of the first exchange: consecutive lane groups of A1
+// threads read rows KG*S1 complex apart; choose S1 so those groups land on
+// disjoint halves of the 64 banks.
+constexpr int pad_s1(int NT, int KG, int A1) {
+    if (A1 >= 32) return 1;
+    for (int pad = 1; pad <= 32; ++pad)
+        if ((KG * (NT + pad)) % 32 == A1 % 32) return pad;
+    return 1;
+}
+
+// Ring spectra layout (the projection's operand): frame b, ring tile
+// rt = r / 16, bin m, part c (0 = re, 1 = im), ring r % 16:
+//   F[(((b * nRT + rt) * M + m) * 2 + c) * 16 + r % 16].
+// Each ring pair writes 8-byte pieces; the workgroup owns all 16 rings of a
+// tile, so every 128-byte line (both parts of one m) is completed by one
+// workgroup within microseconds and leaves L2 as a full line.
+template <typename Real, int A, int A2>
+struct FftLds {
+    using S = FftShape<Real, A>;
+    static constexpr int NT = S::NT, P = S::P, NTHR = S::NTHR;
+    static constexpr int A1 = A / A2;
+    static constexpr int Q = A2 / 16;
+    static constexpr int KG = 16 / Q;
+    static constexpr int S1 = NT + pad_s1(NT, KG, A1);
+    static constexpr int S2 = A1 + 1;
+    static constexpr int XSZ0 = (16 * S1 > A2 * S2) ? 16 * S1 : A2 * S2;
+    static constexpr int XSZ1 = XSZ0 > A ? XSZ0 : A;  // also holds the A gathered samples of a pair
+    // pair slots are 32/P complex (mod 32) apart, so the gather's lanes
+    // (rings fastest, then angles) write to distinct banks
+    static constexpr int SLOT = 32 / P > 0 ? 32 / P : 1;
+    static constexpr int XSZ = XSZ1 + ((SLOT - XSZ1 % 32) % 32 + 32) % 32;
+    static constexpr int NLO = 64;  // two-level table of W_A^x: x = 64 hi + lo
+    static constexpr int NHI = A / NLO > 0 ? A / NLO : 1;
+    // xbuf[P * XSZ], tA2[A2], tLo[NLO], tHi[NHI], w3[A1] (complex), red[NTHR] (float)
+    static constexpr size_t cplx_count = (size_t)P * XSZ + A2 + NLO + NHI + A1;
+    static constexpr size_t bytes = cplx_count * 2 * sizeof(Real) + (size_t)NTHR * sizeof(float);
+};
+
+// One workgroup-tile of the fused resample + FFT: rings
+// [tile * 2 PAIRS, (tile + 1) * 2 PAIRS) of frame img.  smem holds
+// FftLds<Real, A, A2>::bytes bytes (16-byte aligned).
+template <typename Real, int A, int A2>
+__device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, int tile, char* smem) {
+    using C = cplx<Real>;
+    using S = FftShape<Real, A>;
+    using L = FftLds<Real, A, A2>;
+    constexpr int NT = S::NT, P = S::P, NTHR = S::NTHR, ROUNDS = S::ROUNDS, PAIRS = S::PAIRS;
+    constexpr int A1 = L::A1, Q = L::Q, KG = L::KG, S1 = L::S1, S2 = L::S2, XSZ = L::XSZ;
+    constexpr int NLO = L::NLO, NHI = L::NHI;
+    const Real* __restrict__ src = g.src;
+    const long long src_stride = g.src_stride;
+    const int H = g.H, W = g.W, R = g.R, Rp = g.Rp, M = g.M, from_polar = g.from_polar;
+    const double cx = g.cx, cy = g.cy, safe_s = g.safe_s;
+    const double* __restrict__ spx = g.spx;
+    const double* __restrict__ trig = g.trig;
+    Real* __restrict__ F = g.F;
+    float* __restrict__ fmaxbuf = g.fmaxbuf;
+
+    C* xbuf = reinterpret_cast<C*>(smem);
+    C* tA2 = xbuf + P * XSZ;  // W_A2^x  (= W_A^(x A1)), x < A2
+    C* tLo = tA2 + A2;        // W_A^x, x < 64
+    C* tHi = tLo + NLO;       // W_A^(64 x)
+    C* w3 = tHi + NHI;        // exp(+2 pi i a1 / A1)
+    float* red = reinterpret_cast<float*>(w3 + A1);
+
+    const int tid = threadIdx.x;
+    const int f = tid / NT;  // transform slot
+    const int t = tid % NT;  // thread within the transform
+    const int a1 = t % A1;
+    const int q = t / A1;    // phase-1 sub index; also the phase-2 k' group
+    const int r0 = tile * (2 * PAIRS);
+    const int nRT = Rp / zm::kRingTile;
+    const C* twc = reinterpret_cast<const C*>(g.tw);
+    Real* Fimg = F + (size_t)img * nRT * M * 2 * zm::kRingTile;
+
+    if (r0 >= R) {  // padding rings R..Rp-1 are zero
+        for (int e = tid; e < M * 2 * 2 * PAIRS; e += NTHR) {
+            const int row = e / (2 * PAIRS), i = e % (2 * PAIRS);
+            const int r = r0 + i;
+            Fimg[((size_t)(r / zm::kRingTile) * M * 2 + row) * zm::kRingTile + (r % zm::kRingTile)] = (Real)0;
+        }
+        return;
+    }
+
+    // The table entry j holds (cos, sin)(2 pi j / A) = exp(+2 pi i j / A);
+    // multiplying by W^j = exp(-2 pi i j / A) is mulw(z, cos, sin).
+    for (int i = tid; i < A2; i += NTHR) tA2[i] = twc[i * A1];
+    for (int i = tid; i < NLO; i += NTHR) tLo[i] = twc[i < A ? i : 0];
+    for (int i = tid; i < NHI; i += NTHR) tHi[i] = twc[(i * NLO) % A];
+    for (int i = tid; i < A1; i += NTHR) w3[i] = twc[i * A2];  // exp(+2 pi i a1/A1) = W_A1^(a1 (A1-1))
+
+    const Real* frame = src + (size_t)img * (size_t)src_stride;
+    float vmax = 0.f;
+
+    __syncthreads();
+
+    for (int rd = 0; rd < ROUNDS; ++rd) {
+        const int pp = rd * P + f;  // ring pair within the workgroup
+        const int ra = r0 + 2 * pp, rb = ra + 1;
+        C* xb = xbuf + f * XSZ;
+        C z[16];
+        if (from_polar) {
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const int a = t + NT * j;
+                z[j].x = (ra < R) ? frame[(size_t)ra * A + a] : (Real)0;
+                z[j].y = (rb < R) ? frame[(size_t)rb * A + a] : (Real)0;
+            }
+            __syncthreads();  // previous round's phase-3 readers are done
+        } else {
+            // Gather the 2P rings of this round into LDS.  Consecutive lanes
+            // take consecutive rings, then consecutive angles, so one wave
+            // instruction covers a compact (2P rings x 64/2P angles) patch of
+            // the frame.  Each thread keeps one ring and 8 base angles in the
+            // first quadrant; the other 3 quarter turns are exact rotations.
+            const int ri = tid % S::RPR;
+            const int ring = r0 + rd * S::RPR + ri;
+            const double sr = ring < R ? spx[ring] : 0.0;
+            const int last = min(r0 + rd * S::RPR + S::RPR, R) - 1;
+            const bool check = (last >= r0 + rd * S::RPR) && spx[last] >= safe_s;
+            Real* xf = reinterpret_cast<Real*>(xbuf + (ri >> 1) * XSZ) + (ri & 1);
+            __syncthreads();  // previous round's phase-3 readers are done
+#pragma unroll 2
+            for (int i = 0; i < 8; ++i) {
+                const int a = (tid + NTHR * i) / S::RPR;  // base angle, < A / 4
+                const double c = trig[2 * a], sn = trig[2 * a + 1];
+                const double pc = sr * c, ps = sr * sn;
+                // the four quarter turns: x = cx + (pc, -ps, -pc, ps), y = cy - (ps, pc, -ps, -pc);
+                // with 2 cx = W - 1 and 2 cy = H - 1 the negated offsets are mirrors
+                const Coord<Real> xa = split_coord<Real>(cx + pc), xb2 = split_coord<Real>(cx + ps);
+                const Coord<Real> yb = split_coord<Real>(cy + ps), yd = split_coord<Real>(cy + pc);
+                const Coord<Real> xs[4] = {xa, mirror_coord(xb2, W - 1), mirror_coord(xa, W - 1), xb2};
+                const Coord<Real> ys[4] = {mirror_coord(yb, H - 1), mirror_coord(yd, H - 1), yb, yd};
+                Real val[4];
+                if (!check) {
+                    // every ring of the round lies inside the safe radius; rings
+                    // past R (partial last round) sample the centre and are zeroed
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const Real v = bilinear_idx<Real, false>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f);
+                        val[u] = ring < R ? v : (Real)0;
+                    }
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        val[u] = ring < R ? bilinear_idx<Real, true>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f)
+                                          : (Real)0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xf[2 * (a + u * (A / 4))] = val[u];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < 16; ++j) z[j] = xb[t + NT * j];
+        }
+        SmallDft<Real, 16>::run(z);
+        // then W_A2^(q k')
+#pragma unroll
+        for (int k = 1; k < 16; ++k) {
+            const C w = tA2[(q * k) % A2];
+            z[k] = mulw(z[k], w.x, w.y);
+        }
+        __syncthreads();  // all reads of the gathered samples are done
+#pragma unroll
+        for (int k = 0; k < 16; ++k) xb[k * S1 + t] = z[k];
+        __syncthreads();
+        // phase 2: for k' in this thread's group, length-Q DFT over q, then W_A^(a1 k2)
+        C y[KG][Q];
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk) {
+            const int kp = q * KG + kk;
+#pragma unroll
+            for (int qq = 0; qq < Q; ++qq) y[kk][qq] = xb[kp * S1 + a1 + A1 * qq];
+            SmallDft<Real, Q>::run(y[kk]);
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) {
+                const int x = a1 * (kp + 16 * k2);  // < A
+                const C h = tHi[x / NLO], l = tLo[x % NLO];
+                const C w = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
+                y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) xb[((q * KG + kk) + 16 * k2) * S2 + a1] = y[kk][k2];
+        __syncthreads();
+        // phase 3: bins m (k1 = 0) and A - m (k1 = A1 - 1), then split the two rings
+        const int rt = ra / zm::kRingTile, ri = ra % zm::kRingTile;
+        Real* Fo = Fimg + (size_t)rt * M * 2 * zm::kRingTile + ri;
+        for (int m = t; m < M; m += NT) {
+            C pm = {(Real)0, (Real)0};
+#pragma unroll 4
+            for (int i = 0; i < A1; ++i) pm = pm + xb[m * S2 + i];
+            C nm = pm;
+            if (m > 0) {
+                nm = C{(Real)0, (Real)0};
+                const int row = A2 - m;
+#pragma unroll 4
+                for (int i = 0; i < A1; ++i) {
+                    const C v = xb[row * S2 + i];
+                    const C w = w3[i];
+                    nm.x += v.x * w.x - v.y * w.y;
+                    nm.y += v.x * w.y + v.y * w.x;
+                }
+            }
+            // ring a: (X[m] + conj X[A-m]) / 2 ; ring b: (X[m] - conj X[A-m]) / (2 i)
+            const Real fax = (Real)0.5 * (pm.x + nm.x), fay = (Real)0.5 * (pm.y - nm.y);
+            const Real fbx = (Real)0.5 * (pm.y + nm.y), fby = (Real)0.5 * (nm.x - pm.x);
+            vmax = fmaxf(vmax, fmaxf(fmaxf((float)fabs((double)fax), (float)fabs((double)fay)),
+                                     fmaxf((float)fabs((double)fbx), (float)fabs((double)fby))));
+            Real* o = Fo + (size_t)m * 2 * zm::kRingTile;  // ri even: 2-element aligned
+            *reinterpret_cast<Pair2<Real>*>(o) = Pair2<Real>{fax, fbx};
+            *reinterpret_cast<Pair2<Real>*>(o + zm::kRingTile) = Pair2<Real>{fay, fby};
+        }
+    }
+    if (fmaxbuf != nullptr) {
+        red[tid] = vmax;
+        __syncthreads();
+        for (int s = NTHR / 2; s > 0; s >>= 1) {
+            if (tid < s) red[tid] = fmaxf(red[tid], red[tid + s]);
+            __syncthreads();
+        }
+        if (tid == 0) atomicMax(reinterpret_cast<unsigned*>(fmaxbuf) + img, __float_as_uint(red[0]));
+    }
+}
+
+// Standalone launch: one workgroup per (frame, ring tile).  Workgroups are
+// dealt round-robin to the 8 XCDs; renumber them so that each XCD runs a
+// contiguous range of (frame, ring tile) work: tiles running together on one
+// XCD are radial neighbours and share L2 lines (a 128-byte line spans 32
+// rings where the circle runs vertically).
+template <typename Real, int A, int A2>
+__global__ __launch_bounds__((FftShape<Real, A>::NTHR)) __attribute__((amdgpu_waves_per_eu(4))) void polar_fft_kernel(
+    FftArgs<Real> g, int gx, int G) {
+    __shared__ __attribute__((aligned(16))) char smem[FftLds<Real, A, A2>::bytes];
+    const int per_xcd = (int)(gridDim.x / 8);
+    const int lid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (lid >= G) return;
+    polar_fft_tile<Real, A, A2>(g, lid / gx, lid % gx, smem);
+}
+
+}  // namespace zmk

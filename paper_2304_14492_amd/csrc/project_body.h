@@ -1,0 +1,237 @@
+// Device body of the radial projection on MFMA (see project.hip for the
+// method); shared by the standalone kernel and the persistent batch kernel.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "zm_internal.h"
+
+namespace zmk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
+typedef float float8 __attribute__((ext_vector_type(8)));
+
+constexpr int kWaves = 4;
+
+__device__ __forceinline__ int out_index(int n, int m) { return zm::canon_index(n, m); }
+
+
+// frame scale for the F16 split: 2^e with max|F| * 2^e in [2^13, 2^14)
+__device__ __forceinline__ float f16_frame_scale(float mx) {
+    if (!(mx > 0.f)) return 1.f;
+    int ex;
+    frexpf(mx, &ex);
+    return ldexpf(1.f, 14 - ex);
+}
+
+struct ProjArgs {
+    const zm_item* items;
+    int n_units, ncb;
+    const void* thi;
+    const void* tlo;
+    const float* rowscale;
+    const void* F;
+    const float* fmaxbuf;
+    int B, M, Rp, Mtot;
+    void* Z;             // contiguous [B][Mtot][2], or null
+    void* const* Zptrs;  // per-frame outputs (used when Z is null)
+};
+
+template <typename T>
+__device__ __forceinline__ T* zbase(const ProjArgs& a, int fr) {
+    return a.Z ? (T*)a.Z + (size_t)fr * a.Mtot * 2 : (T*)a.Zptrs[fr];
+}
+
+// One wave: output block `unit` = (item unit / ncb, column block unit % ncb).
+template <int DT>
+__device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int lane) {
+    const zm_item* __restrict__ items = a.items;
+    const void* __restrict__ thi = a.thi;
+    const void* __restrict__ tlo = a.tlo;
+    const float* __restrict__ rowscale = a.rowscale;
+    const void* __restrict__ Fv = a.F;
+    const float* __restrict__ fmaxbuf = a.fmaxbuf;
+    const int B = a.B, M = a.M, Rp = a.Rp, ncb = a.ncb;
+    const int li = lane & 15, lg = lane >> 4;
+    const int cb = unit % ncb;
+    const zm_item it = items[unit / ncb];
+    const int m = it.m;
+    const bool two = it.rows > 16;  // wave-uniform
+
+    // the two 16-column sub-tiles: column = 2 * frame + (re|im); a column's
+    // rings k sit at boff + (k / 16) * TS + k % 16
+    const int nRT = Rp / zm::kRingTile;
+    const size_t TS = (size_t)M * 2 * zm::kRingTile;
+    int col[2], fr[2];
+    size_t boff[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        col[u] = cb * 32 + 16 * u + li;
+        fr[u] = col[u] >> 1;
+        const int frc = fr[u] < B ? fr[u] : B - 1;  // clamp: loads stay in bounds, results discarded
+        boff[u] = ((size_t)frc * nRT * M + m) * 2 * zm::kRingTile + (size_t)(col[u] & 1) * zm::kRingTile;
+    }
+    size_t aoff[2];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) aoff[s] = (size_t)(it.toff + it.row0 + 16 * s + li) * Rp;
+
+    if constexpr (DT == ZM_F64) {
+        const double* T = (const double*)thi;
+        const double* F = (const double*)Fv;
+        doublex4 acc[2][2] = {};
+        for (int k0 = 0; k0 < Rp; k0 += 16) {
+            const int kk = k0 + 4 * lg;
+            double a[2][4], b[2][4];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                if (s == 1 && !two) break;
+                const double2 x0 = *(const double2*)(T + aoff[s] + kk);
+                const double2 x1 = *(const double2*)(T + aoff[s] + kk + 2);
+                a[s][0] = x0.x; a[s][1] = x0.y; a[s][2] = x1.x; a[s][3] = x1.y;
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const size_t fo = boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg;
+                const double2 y0 = *(const double2*)(F + fo);
+                const double2 y1 = *(const double2*)(F + fo + 2);
+                b[u][0] = y0.x; b[u][1] = y0.y; b[u][2] = y1.x; b[u][3] = y1.y;
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    if (s == 1 && !two) break;
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][v], b[u][v], acc[s][u], 0, 0, 0);
+                }
+        }
+        const int kmrows = (M - 1 - m) / 2 + 1;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = it.row0 + 16 * s + lg + 4 * v;  // FP64 MFMA output: row lane/16 + 4 v
+                    if ((s == 0 || two) && row < kmrows && fr[u] < B)
+                        zbase<double>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = acc[s][u][v];
+                }
+    } else if constexpr (DT == ZM_F32) {
+        const float* T = (const float*)thi;
+        const float* F = (const float*)Fv;
+        floatx4 acc[2][2] = {};
+        for (int k0 = 0; k0 < Rp; k0 += 16) {
+            const int kk = k0 + 4 * lg;
+            float4 a[2], b[2];
+            a[0] = *(const float4*)(T + aoff[0] + kk);
+            if (two) a[1] = *(const float4*)(T + aoff[1] + kk);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) b[u] = *(const float4*)(F + boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg);
+            const float av[2][4] = {{a[0].x, a[0].y, a[0].z, a[0].w}, {a[1].x, a[1].y, a[1].z, a[1].w}};
+            const float bv[2][4] = {{b[0].x, b[0].y, b[0].z, b[0].w}, {b[1].x, b[1].y, b[1].z, b[1].w}};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+#pragma unroll
+                for (int u = 0; u < 2; ++u)
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][v], bv[u][v], acc[0][u], 0, 0, 0);
+                if (two) {
+#pragma unroll
+                    for (int u = 0; u < 2; ++u)
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][v], bv[u][v], acc[1][u], 0, 0, 0);
+                }
+            }
+        }
+        const int kmrows = (M - 1 - m) / 2 + 1;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = it.row0 + 16 * s + 4 * lg + v;
+                    if ((s == 0 || two) && row < kmrows && fr[u] < B)
+                        zbase<float>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = acc[s][u][v];
+                }
+    } else {
+        // split forms: 16-bit hi/lo operands, K step 32 (8 consecutive rings per lane group)
+        using H8 = typename std::conditional<DT == ZM_BF16X2, bf16x8, halfx8>::type;
+        using H1 = typename std::conditional<DT == ZM_BF16X2, __bf16, _Float16>::type;
+        const H1* Th = (const H1*)thi;
+        const H1* Tl = (const H1*)tlo;
+        const float* F = (const float*)Fv;
+        float fsc[2] = {1.f, 1.f};
+        if constexpr (DT == ZM_F16X2) {
+#pragma unroll
+            for (int u = 0; u < 2; ++u) fsc[u] = f16_frame_scale(fmaxbuf[fr[u] < B ? fr[u] : B - 1]);
+        }
+        floatx4 acc[2][2] = {};
+        for (int k0 = 0; k0 < Rp; k0 += 32) {
+            const int kk = k0 + 8 * lg;
+            H8 ah[2], al[2], bh[2], bl[2];
+            ah[0] = *(const H8*)(Th + aoff[0] + kk);
+            al[0] = *(const H8*)(Tl + aoff[0] + kk);
+            if (two) {
+                ah[1] = *(const H8*)(Th + aoff[1] + kk);
+                al[1] = *(const H8*)(Tl + aoff[1] + kk);
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const size_t fo = boff[u] + (size_t)((k0 >> 4) + (lg >> 1)) * TS + 8 * (lg & 1);
+                const float4 y0 = *(const float4*)(F + fo);
+                const float4 y1 = *(const float4*)(F + fo + 4);
+                const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const float x = yv[e] * fsc[u];
+                    const H1 h = (H1)x;
+                    bh[u][e] = h;
+                    bl[u][e] = (H1)(x - (float)h);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if constexpr (DT == ZM_BF16X2) {
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0], bh[u], acc[0][u], 0, 0, 0);
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[0], bl[u], acc[0][u], 0, 0, 0);
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[0], bh[u], acc[0][u], 0, 0, 0);
+                    if (two) {
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[1], bh[u], acc[1][u], 0, 0, 0);
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[1], bl[u], acc[1][u], 0, 0, 0);
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[1], bh[u], acc[1][u], 0, 0, 0);
+                    }
+                } else {
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[0], bh[u], acc[0][u], 0, 0, 0);
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[0], bl[u], acc[0][u], 0, 0, 0);
+                    acc[0][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[0], bh[u], acc[0][u], 0, 0, 0);
+                    if (two) {
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[1], bh[u], acc[1][u], 0, 0, 0);
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[1], bl[u], acc[1][u], 0, 0, 0);
+                        acc[1][u] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[1], bh[u], acc[1][u], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        const int kmrows = (M - 1 - m) / 2 + 1;
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = it.row0 + 16 * s + 4 * lg + v;
+                    if ((s == 0 || two) && row < kmrows && fr[u] < B) {
+                        float val = acc[s][u][v];
+                        if constexpr (DT == ZM_F16X2) val = val * rowscale[it.toff + row] / fsc[u];
+                        zbase<float>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = val;
+                    }
+                }
+    }
+}
+
+}  // namespace zmk
