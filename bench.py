@@ -13,6 +13,13 @@ Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
   projection     the projection kernel's useful FLOP rate vs the MFMA peak
   split_bf16     the same step with the hi/lo split-BF16 projection
   cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s
+  batch_form     64 mixed square frames (sides 256..2048, N_max 30/50/100) in
+                 one persistent launch replayed from a HIP graph
+  latency        the serving form: Poisson arrivals at a fixed rate of
+                 640x480 / 1080p / 4K frames (N_max 30/100/200) from pinned host
+                 memory, continuous batching under an HBM budget; p50 / p99 /
+                 p99.9 latency (arrival -> moments in host memory), FP32 and
+                 split-BF16 projection
 """
 from __future__ import annotations
 
@@ -131,6 +138,47 @@ def cpu_baseline(budget_s):
                        "exact radial table built once beforehand (plan-time, untimed)")
 
 
+def batch_form(steps):
+    import torch
+    import paper_2304_14492_amd as zm
+    import synth
+    from synth.frames import FrameSpec
+    specs = synth.batch_sides(64, seed=4)
+    frames, plans, cache = [], [], {}
+    for side, nmax, seed in specs:
+        frames.append(torch.from_numpy(synth.make_frame(FrameSpec(side, side, blobs=8), seed)).cuda())
+        if (side, nmax) not in cache:
+            cache[(side, nmax)] = zm.Plan(nmax, side, side, dtype="f32")
+        plans.append(cache[(side, nmax)])
+    b = zm.Batch(plans, frames, autotune=True, graph=True)
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    b.check()
+    ms = e0.elapsed_time(e1) / steps
+    cfg = b.config()
+    b.close()
+    return {"images_per_s": round(len(frames) / (ms / 1e3), 1), "ms_per_batch": round(ms, 4), "frames": len(frames),
+            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "queue_items": cfg["n_items"]}
+
+
+def serving(dtype, count, qps, warmup_s):
+    from paper_2304_14492_amd import serve
+    reqs = serve.make_requests(count, qps, seed=5, pool_per_size=3)
+    dev = serve.GpuDevice(dtype=dtype, n_streams=4)
+    dev.warm({(r.H, r.W, r.nmax) for r in reqs})
+    sch = serve.Scheduler(dev, budget_bytes=4 << 30, max_inflight=8, max_batch=8)
+    done = serve.run_stream(reqs, sch)
+    st = serve.latency_stats(done, warmup_s=warmup_s)
+    st.update(qps=qps, requests=count, warmup_s=warmup_s, dtype=dtype, peak_budget_bytes=sch.peak_used)
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +188,12 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16x2", "f16x2"])
     ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="0 skips the CPU baseline")
+    ap.add_argument("--qps", type=float, default=1000.0, help="serving arrival rate")
+    ap.add_argument("--requests", type=int, default=3000, help="serving requests per dtype (0 skips serving)")
+    ap.add_argument("--no-batch-form", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times): the reference for scaling "
+                         "the FETCH_SIZE / WRITE_SIZE counters into bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: every frame is independent (images shard with no "
@@ -148,6 +202,17 @@ def main():
 
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy > 0:
+        n = args.calibrate_copy * (1 << 20) // 4
+        src = torch.rand(n, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_mib": args.calibrate_copy, "bytes_read_per_copy": 4 * n,
+                          "bytes_written_per_copy": 4 * n}))
+        return
     print(f"[bench] batch={args.batch} steps={args.steps} warmup={args.warmup} dtype={args.dtype}",
           file=sys.stderr, flush=True)
     r = run_gpu(args.batch, args.steps, args.warmup, args.dtype)
@@ -193,6 +258,16 @@ def main():
                              "ms_per_step": round(ms2, 4), "projection_ms": round(r2["proj_ms"], 4),
                              "projection_useful_tflops": round(flops_launch / (r2["proj_ms"] / 1e3) / 1e12, 2)}
         print(f"[bench] bf16x2: {ms2:.3f} ms/step, projection {r2['proj_ms']:.3f} ms", file=sys.stderr, flush=True)
+    if not args.no_batch_form:
+        torch.cuda.empty_cache()
+        res["batch_form"] = batch_form(args.steps)
+        print(f"[bench] batch form: {res['batch_form']}", file=sys.stderr, flush=True)
+    if args.requests > 0:
+        torch.cuda.empty_cache()
+        res["latency"] = {}
+        for dt in ("f32", "bf16x2"):
+            res["latency"][dt] = serving(dt, args.requests, args.qps, warmup_s=0.5)
+            print(f"[bench] serving {dt}: {res['latency'][dt]}", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)

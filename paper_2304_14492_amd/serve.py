@@ -1,0 +1,282 @@
+"""Serving form: continuous batching of moment requests on one GPU.
+
+Requests arrive over time (frames of mixed sizes and orders).  The scheduler
+admits them in arrival order as device memory (an HBM byte budget) and launch
+slots free up, groups admitted requests that share a plan into one launch,
+and spreads launches over several HIP streams so that the work of requests
+admitted at different times overlaps on the device.  Plans (radial tables
+and projection operands) stay resident.  Latency = completion time - arrival
+time, where completion means the moments are back in host memory.
+
+The policy (`Scheduler`) is device-agnostic: `GpuDevice` runs it on the
+library, `FakeDevice` + `FakeClock` run it on the CPU for tests.
+"""
+from __future__ import annotations
+
+import collections
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+@dataclass
+class Request:
+    rid: int
+    t_arrival: float
+    H: int
+    W: int
+    nmax: int
+    frame: object = None          # host frame (numpy float32, pinned torch tensor, ...)
+    t_admit: float = math.nan
+    t_done: float = math.nan
+    result: object = None
+    nbytes: int = 0
+
+
+@dataclass
+class Launch:
+    key: tuple
+    reqs: list
+    nbytes: int
+    handle: object = None
+    t_launch: float = 0.0
+
+
+class Scheduler:
+    """FIFO admission under a byte budget and an in-flight launch cap; admitted
+    requests with the same plan key are launched together (up to max_batch)."""
+
+    def __init__(self, device, budget_bytes: int, max_inflight: int = 8, max_batch: int = 16):
+        self.dev = device
+        self.budget = int(budget_bytes)
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.waiting = collections.deque()
+        self.inflight: list[Launch] = []
+        self.used = 0
+        self.peak_used = 0
+        self.done: list[Request] = []
+
+    def submit(self, req: Request):
+        req.nbytes = self.dev.request_bytes(req)
+        if req.nbytes > self.budget:
+            raise ValueError(f"request {req.rid} needs {req.nbytes} bytes, more than the whole budget")
+        self.waiting.append(req)
+
+    def _admit(self, now: float):
+        # head-of-line FIFO: admit from the front while it fits; gather requests
+        # of the same plan from the admitted prefix into one launch
+        admitted = []
+        room = (self.max_inflight - len(self.inflight)) * self.max_batch
+        while self.waiting and len(admitted) < room:
+            r = self.waiting[0]
+            if self.used + r.nbytes > self.budget:
+                break
+            self.waiting.popleft()
+            self.used += r.nbytes
+            self.peak_used = max(self.peak_used, self.used)
+            r.t_admit = now
+            admitted.append(r)
+        groups = collections.OrderedDict()
+        for r in admitted:
+            groups.setdefault(self.dev.plan_key(r), []).append(r)
+        out = []
+        for key, rs in groups.items():
+            for i in range(0, len(rs), self.max_batch):
+                chunk = rs[i:i + self.max_batch]
+                out.append(Launch(key=key, reqs=chunk, nbytes=sum(r.nbytes for r in chunk)))
+        return out
+
+    def step(self, now: float):
+        """Retire finished launches, then admit and launch what fits."""
+        still = []
+        for ln in self.inflight:
+            if self.dev.is_done(ln):
+                self.dev.finish(ln)
+                for r in ln.reqs:
+                    r.t_done = now  # completion observed at this poll
+                    self.done.append(r)
+                self.used -= ln.nbytes
+            else:
+                still.append(ln)
+        self.inflight = still
+        if len(self.inflight) < self.max_inflight:
+            for ln in self._admit(now):
+                ln.t_launch = now
+                self.dev.launch(ln)
+                self.inflight.append(ln)
+
+    def idle(self):
+        return not self.waiting and not self.inflight
+
+
+def run_stream(requests, scheduler: Scheduler, clock=time.perf_counter, sleep=None):
+    """Replay `requests` (t_arrival in seconds from the start) through the
+    scheduler in real (or fake) time.  Returns the completed requests with
+    t_admit / t_done on the same time axis as t_arrival."""
+    pending = collections.deque(sorted(requests, key=lambda r: r.t_arrival))
+    start = clock()
+    while pending or not scheduler.idle():
+        now = clock() - start
+        while pending and pending[0].t_arrival <= now:
+            scheduler.submit(pending.popleft())
+        scheduler.step(now)
+        if sleep is not None:
+            sleep()
+    return scheduler.done
+
+
+def latency_stats(done, warmup_s: float = 0.0):
+    lat = np.array([r.t_done - r.t_arrival for r in done if r.t_arrival >= warmup_s])
+    if lat.size == 0:
+        return {}
+    span = max(r.t_done for r in done) - min(r.t_arrival for r in done)
+    return dict(count=int(lat.size), p50_ms=float(np.percentile(lat, 50) * 1e3),
+                p99_ms=float(np.percentile(lat, 99) * 1e3), p999_ms=float(np.percentile(lat, 99.9) * 1e3),
+                mean_ms=float(lat.mean() * 1e3), images_per_s=float(len(done) / span) if span > 0 else 0.0)
+
+
+# --------------------------------------------------------------------------
+# Devices
+# --------------------------------------------------------------------------
+class FakeClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def advance(self, dt=1e-5):
+        self.t += dt
+
+
+class FakeDevice:
+    """Completes a launch a fixed time per request after it starts; used to
+    test the scheduling policy on the CPU."""
+
+    def __init__(self, clock: FakeClock, bytes_per_pixel: int = 12, service_s_per_mpix: float = 1e-4):
+        self.clock = clock
+        self.bpp = bytes_per_pixel
+        self.svc = service_s_per_mpix
+        self.launched = []
+
+    def request_bytes(self, r: Request) -> int:
+        return self.bpp * r.H * r.W
+
+    def plan_key(self, r: Request):
+        return (r.H, r.W, r.nmax)
+
+    def launch(self, ln: Launch):
+        dur = sum(self.svc * r.H * r.W / 1e6 for r in ln.reqs)
+        ln.handle = self.clock() + dur
+        self.launched.append(ln)
+
+    def is_done(self, ln: Launch) -> bool:
+        return self.clock() >= ln.handle
+
+    def finish(self, ln: Launch):
+        for r in ln.reqs:
+            r.result = ("done", r.rid)
+
+
+class GpuDevice:
+    """Runs launches on the library: pinned host frames -> device (copy
+    stream), zm_moments on one of several compute streams, moments -> pinned
+    host buffers (copy stream); an event marks completion."""
+
+    def __init__(self, dtype: str = "f32", n_streams: int = 4, plans=None):
+        import torch
+
+        import paper_2304_14492_amd as zm
+        self.zm = zm
+        self.torch = torch
+        self.dtype = dtype
+        self.plans = dict(plans or {})
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.copy_in = torch.cuda.Stream()
+        self.copy_out = torch.cuda.Stream()
+        self.rr = 0
+
+    def plan(self, H, W, nmax):
+        key = (H, W, nmax)
+        if key not in self.plans:
+            self.plans[key] = self.zm.Plan(nmax, H, W, dtype=self.dtype)
+        return self.plans[key]
+
+    def plan_key(self, r: Request):
+        return (r.H, r.W, r.nmax)
+
+    def request_bytes(self, r: Request) -> int:
+        p = self.plan(r.H, r.W, r.nmax)
+        return 4 * r.H * r.W + p.workspace_size(1) + 8 * p.num_moments
+
+    def launch(self, ln: Launch):
+        torch = self.torch
+        H, W, nmax = ln.key
+        p = self.plan(H, W, nmax)
+        B = len(ln.reqs)
+        cs = self.streams[self.rr % len(self.streams)]
+        self.rr += 1
+        frames = torch.empty(B, H, W, dtype=torch.float32, device="cuda")
+        ws = p.workspace(B)
+        Z = torch.empty(B, p.num_moments, 2, dtype=torch.float32, device="cuda")
+        host_out = torch.empty(B, p.num_moments, 2, dtype=torch.float32, pin_memory=True)
+        with torch.cuda.stream(self.copy_in):
+            for i, r in enumerate(ln.reqs):
+                frames[i].copy_(r.frame, non_blocking=True)
+            ev_in = torch.cuda.Event()
+            ev_in.record(self.copy_in)
+        cs.wait_event(ev_in)
+        p.moments(frames, out=Z, workspace=ws, stream=cs)
+        ev_c = torch.cuda.Event()
+        ev_c.record(cs)
+        self.copy_out.wait_event(ev_c)
+        with torch.cuda.stream(self.copy_out):
+            host_out.copy_(Z, non_blocking=True)
+            ev_done = torch.cuda.Event()
+            ev_done.record(self.copy_out)
+        # keep device buffers alive until the launch retires
+        frames.record_stream(self.copy_in)
+        frames.record_stream(cs)
+        Z.record_stream(cs)
+        Z.record_stream(self.copy_out)
+        ws.record_stream(cs)
+        ln.handle = (ev_done, frames, ws, Z, host_out)
+
+    def is_done(self, ln: Launch) -> bool:
+        return ln.handle[0].query()
+
+    def finish(self, ln: Launch):
+        host_out = ln.handle[4]
+        for i, r in enumerate(ln.reqs):
+            r.result = host_out[i]
+        ln.handle = None
+
+    def warm(self, keys):
+        """Create the resident plans for these (H, W, nmax) keys up front."""
+        for H, W, nmax in keys:
+            self.plan(H, W, nmax)
+
+
+def make_requests(count: int, qps: float, seed: int = 5, pool_per_size: int = 3, pin: bool = True):
+    """Poisson stream (synth.request_stream); frames come from a pool of
+    `pool_per_size` seeded frames per size (request seed mod pool)."""
+    import synth
+    from synth.frames import FrameSpec
+    stream = synth.request_stream(count, qps, seed=seed)
+    pool = {}
+    reqs = []
+    for i, (t, H, W, nmax, fseed) in enumerate(stream):
+        k = (H, W, fseed % pool_per_size)
+        if k not in pool:
+            f = synth.make_frame(FrameSpec(H, W, blobs=16, polygons=8, noise=False, zero_outside=False),
+                                 seed=5000 + fseed % pool_per_size)
+            if pin:
+                import torch
+                pool[k] = torch.from_numpy(f).pin_memory()
+            else:
+                pool[k] = f
+        reqs.append(Request(rid=i, t_arrival=t, H=H, W=W, nmax=nmax, frame=pool[k]))
+    return reqs
