@@ -19,7 +19,8 @@ Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
                  640x480 / 1080p / 4K frames (N_max 30/100/200) from pinned host
                  memory, continuous batching under an HBM budget; p50 / p99 /
                  p99.9 latency (arrival -> moments in host memory), FP32 and
-                 split-BF16 projection
+                 split-BF16 projection; saturation throughput from a burst,
+                 then streams at the fixed rate and at 50 % / 80 % of it
 """
 from __future__ import annotations
 
@@ -168,15 +169,39 @@ def batch_form(steps):
 
 
 def serving(dtype, count, qps, warmup_s):
+    """Serving form for one projection dtype: saturation throughput (every
+    request queued at t = 0), then Poisson streams at the fixed rate `qps` and
+    at 50 % / 80 % of the measured saturation."""
     from paper_2304_14492_amd import serve
-    reqs = serve.make_requests(count, qps, seed=5, pool_per_size=3)
     dev = serve.GpuDevice(dtype=dtype, n_streams=4)
-    dev.warm({(r.H, r.W, r.nmax) for r in reqs})
-    sch = serve.Scheduler(dev, budget_bytes=4 << 30, max_inflight=8, max_batch=8)
-    done = serve.run_stream(reqs, sch)
-    st = serve.latency_stats(done, warmup_s=warmup_s)
-    st.update(qps=qps, requests=count, warmup_s=warmup_s, dtype=dtype, peak_budget_bytes=sch.peak_used)
-    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+
+    def one(rate, n, burst=False):
+        reqs = serve.make_requests(n, rate, seed=5, pool_per_size=3)
+        if burst:
+            for r in reqs:
+                r.t_arrival = 0.0
+        dev.warm({(r.H, r.W, r.nmax) for r in reqs})
+        sch = serve.Scheduler(dev, budget_bytes=4 << 30, max_inflight=8, max_batch=8)
+        done = serve.run_stream(reqs, sch)
+        st = serve.latency_stats(done, warmup_s=0.0 if burst else warmup_s, by_size=not burst)
+        st.update(qps=None if burst else rate, requests=n, peak_budget_bytes=sch.peak_used)
+        return st
+
+    sat = one(qps, max(count // 4, 200), burst=True)["images_per_s"]
+    out = {"dtype": dtype, "warmup_s": warmup_s, "saturation_images_per_s": sat, "runs": []}
+    for rate in (qps, 0.5 * sat, 0.8 * sat):
+        n = int(min(count, max(200, rate * (warmup_s + 8.0))))  # about 8 s after the warm-up
+        out["runs"].append(one(rate, n))
+
+    def rnd(v):
+        if isinstance(v, float):
+            return round(v, 4)
+        if isinstance(v, dict):
+            return {k: rnd(x) for k, x in v.items()}
+        if isinstance(v, list):
+            return [rnd(x) for x in v]
+        return v
+    return rnd(out)
 
 
 def main():
@@ -189,7 +214,8 @@ def main():
     ap.add_argument("--no-split", action="store_true", help="skip the split-BF16 comparison run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0, help="0 skips the CPU baseline")
     ap.add_argument("--qps", type=float, default=1000.0, help="serving arrival rate")
-    ap.add_argument("--requests", type=int, default=3000, help="serving requests per dtype (0 skips serving)")
+    ap.add_argument("--requests", type=int, default=10000,
+                    help="at most this many requests per serving run (0 skips serving)")
     ap.add_argument("--no-batch-form", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for scaling "
@@ -266,7 +292,7 @@ def main():
         torch.cuda.empty_cache()
         res["latency"] = {}
         for dt in ("f32", "bf16x2"):
-            res["latency"][dt] = serving(dt, args.requests, args.qps, warmup_s=0.5)
+            res["latency"][dt] = serving(dt, args.requests, args.qps, warmup_s=2.0)
             print(f"[bench] serving {dt}: {res['latency'][dt]}", file=sys.stderr, flush=True)
     if args.cpu_seconds > 0:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)

@@ -200,15 +200,15 @@ struct FftArgs {
     float* fmaxbuf;        // per-frame max |F| (FP16 split) or null
 };
 
-template <typename Real, int A>
+template <typename Real, int A, int WG = 512, int TP = 8>
 struct FftShape {
     static constexpr int NT = A / 16;  // threads per transform
-    // transforms (ring pairs) in flight: 512 threads per workgroup for FP32
-    // with A >= 512 (two workgroups per CU at A = 4096), at most 8 otherwise
-    static constexpr bool kWide = A >= 512 && sizeof(Real) == 4;
-    static constexpr int P = kWide ? 512 / NT : ((512 / NT) > 8 ? 8 : (512 / NT));
+    // transforms (ring pairs) in flight: WG threads per workgroup for FP32
+    // with A >= WG, at most 8 transforms otherwise
+    static constexpr bool kWide = A >= WG && sizeof(Real) == 4;
+    static constexpr int P = kWide ? WG / NT : ((WG / NT) > 8 ? 8 : (WG / NT));
     static constexpr int NTHR = NT * P;               // workgroup size
-    static constexpr int PAIRS = P > 8 ? P : 8;       // ring pairs per workgroup (16 or 32 rings)
+    static constexpr int PAIRS = P > TP ? P : TP;     // ring pairs per workgroup
     static constexpr int ROUNDS = PAIRS / P;
     static constexpr int RPR = 2 * P;                 // rings gathered per round
 };
@@ -229,9 +229,9 @@ constexpr int pad_s1(int NT, int KG, int A1) {
 // Each ring pair writes 8-byte pieces; the workgroup owns all 16 rings of a
 // tile, so every 128-byte line (both parts of one m) is completed by one
 // workgroup within microseconds and leaves L2 as a full line.
-template <typename Real, int A, int A2>
+template <typename Real, int A, int A2, int WG = 512, int TP = 8>
 struct FftLds {
-    using S = FftShape<Real, A>;
+    using S = FftShape<Real, A, WG, TP>;
     static constexpr int NT = S::NT, P = S::P, NTHR = S::NTHR;
     static constexpr int A1 = A / A2;
     static constexpr int Q = A2 / 16;
@@ -254,11 +254,11 @@ struct FftLds {
 // One workgroup-tile of the fused resample + FFT: rings
 // [tile * 2 PAIRS, (tile + 1) * 2 PAIRS) of frame img.  smem holds
 // FftLds<Real, A, A2>::bytes bytes (16-byte aligned).
-template <typename Real, int A, int A2>
+template <typename Real, int A, int A2, int WG = 512, int TP = 8>
 __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, int tile, char* smem) {
     using C = cplx<Real>;
-    using S = FftShape<Real, A>;
-    using L = FftLds<Real, A, A2>;
+    using S = FftShape<Real, A, WG, TP>;
+    using L = FftLds<Real, A, A2, WG, TP>;
     constexpr int NT = S::NT, P = S::P, NTHR = S::NTHR, ROUNDS = S::ROUNDS, PAIRS = S::PAIRS;
     constexpr int A1 = L::A1, Q = L::Q, KG = L::KG, S1 = L::S1, S2 = L::S2, XSZ = L::XSZ;
     constexpr int NLO = L::NLO, NHI = L::NHI;
@@ -323,29 +323,46 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
             }
             __syncthreads();  // previous round's phase-3 readers are done
         } else {
-            // Gather the 2P rings of this round into LDS.  Consecutive lanes
-            // take consecutive rings, then consecutive angles, so one wave
-            // instruction covers a compact (2P rings x 64/2P angles) patch of
-            // the frame.  Each thread keeps one ring and 8 base angles in the
-            // first quadrant; the other 3 quarter turns are exact rotations.
-            const int ri = tid % S::RPR;
-            const int ring = r0 + rd * S::RPR + ri;
-            const double sr = ring < R ? spx[ring] : 0.0;
-            const int last = min(r0 + rd * S::RPR + S::RPR, R) - 1;
-            const bool check = (last >= r0 + rd * S::RPR) && spx[last] >= safe_s;
-            Real* xf = reinterpret_cast<Real*>(xbuf + (ri >> 1) * XSZ) + (ri & 1);
+            // Gather the 2P rings of this round into LDS.  A wave instruction
+            // covers a compact patch of 2P rings x 64/2P consecutive angles.
+            // The texture path coalesces within groups of 4 lanes, so the
+            // lanes of a group should read neighbouring pixels of one row:
+            // where the ring runs vertically (angle within 45 deg of the x
+            // axis) the 4 lanes take 4 consecutive rings at one angle ("V"),
+            // where it runs horizontally 4 consecutive angles of one ring
+            // ("H").  Both lane maps cover the same patch.  Each thread works
+            // on base angles in the first quadrant; the other 3 quarter turns
+            // are exact rotations, and turns 0, 2 and turns 1, 3 fall in
+            // opposite kinds of octant.
+            const int rbase = r0 + rd * S::RPR;
+            const int last = min(rbase + S::RPR, R) - 1;
+            const bool check = (last >= rbase) && spx[last] >= safe_s;
+            const int ri_v = tid % S::RPR;
+            const double sr_v = rbase + ri_v < R ? spx[rbase + ri_v] : 0.0;
+            Real* xf_v = reinterpret_cast<Real*>(xbuf + (ri_v >> 1) * XSZ) + (ri_v & 1);
             __syncthreads();  // previous round's phase-3 readers are done
 #pragma unroll 2
             for (int i = 0; i < 8; ++i) {
-                const int a = (tid + NTHR * i) / S::RPR;  // base angle, < A / 4
-                const double c = trig[2 * a], sn = trig[2 * a + 1];
-                const double pc = sr * c, ps = sr * sn;
-                // the four quarter turns: x = cx + (pc, -ps, -pc, ps), y = cy - (ps, pc, -ps, -pc);
+                const int a_v = (tid + NTHR * i) / S::RPR;  // base angle, < A / 4
+                const int rest = (tid + NTHR * i) >> 2;
+                const int ri_h = rest % S::RPR;
+                const int a_h = (rest / S::RPR) * 4 + (tid & 3);
+                // iterations 0..3 hold the base angles below A / 8 (both lane maps)
+                const bool low = i < 4;
+                // turns 0, 2 use (ring, angle) p; turns 1, 3 use q
+                const int ri_p = low ? ri_v : ri_h, a_p = low ? a_v : a_h;
+                const int ri_q = low ? ri_h : ri_v, a_q = low ? a_h : a_v;
+                const double sr_h = rbase + ri_h < R ? spx[rbase + ri_h] : 0.0;
+                const double sr_p = low ? sr_v : sr_h, sr_q = low ? sr_h : sr_v;
+                const double pc = sr_p * trig[2 * a_p], ps = sr_p * trig[2 * a_p + 1];
+                const double qc = sr_q * trig[2 * a_q], qs = sr_q * trig[2 * a_q + 1];
+                // the four quarter turns of (c, s): x = cx + (c, -s, -c, s), y = cy - (s, c, -s, -c);
                 // with 2 cx = W - 1 and 2 cy = H - 1 the negated offsets are mirrors
-                const Coord<Real> xa = split_coord<Real>(cx + pc), xb2 = split_coord<Real>(cx + ps);
-                const Coord<Real> yb = split_coord<Real>(cy + ps), yd = split_coord<Real>(cy + pc);
+                const Coord<Real> xa = split_coord<Real>(cx + pc), yb = split_coord<Real>(cy + ps);
+                const Coord<Real> xb2 = split_coord<Real>(cx + qs), yd = split_coord<Real>(cy + qc);
                 const Coord<Real> xs[4] = {xa, mirror_coord(xb2, W - 1), mirror_coord(xa, W - 1), xb2};
                 const Coord<Real> ys[4] = {mirror_coord(yb, H - 1), mirror_coord(yd, H - 1), yb, yd};
+                const bool in_p = rbase + ri_p < R, in_q = rbase + ri_q < R;
                 Real val[4];
                 if (!check) {
                     // every ring of the round lies inside the safe radius; rings
@@ -353,16 +370,22 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
                         const Real v = bilinear_idx<Real, false>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f);
-                        val[u] = ring < R ? v : (Real)0;
+                        val[u] = ((u & 1) ? in_q : in_p) ? v : (Real)0;
                     }
                 } else {
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
-                        val[u] = ring < R ? bilinear_idx<Real, true>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f)
-                                          : (Real)0;
+                        val[u] = ((u & 1) ? in_q : in_p)
+                                     ? bilinear_idx<Real, true>(frame, H, W, xs[u].i, ys[u].i, xs[u].f, ys[u].f)
+                                     : (Real)0;
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) xf[2 * (a + u * (A / 4))] = val[u];
+                Real* xf_h = reinterpret_cast<Real*>(xbuf + (ri_h >> 1) * XSZ) + (ri_h & 1);
+                Real* xf_p = low ? xf_v : xf_h;
+                Real* xf_q = low ? xf_h : xf_v;
+                xf_p[2 * a_p] = val[0];
+                xf_q[2 * (a_q + A / 4)] = val[1];
+                xf_p[2 * (a_p + A / 2)] = val[2];
+                xf_q[2 * (a_q + 3 * (A / 4))] = val[3];
             }
             __syncthreads();
 #pragma unroll
@@ -387,12 +410,25 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
 #pragma unroll
             for (int qq = 0; qq < Q; ++qq) y[kk][qq] = xb[kp * S1 + a1 + A1 * qq];
             SmallDft<Real, Q>::run(y[kk]);
+            if constexpr (A1 <= 16) {
+                // W_A^(a1 kp) W_A^(16 a1 k2); A1 divides 16, so the second factor is a W_A2 table entry
+                const int x0 = a1 * kp;  // < 16 A1 <= A
+                const C h = tHi[x0 / NLO], l = tLo[x0 % NLO];
+                const C b = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
 #pragma unroll
-            for (int k2 = 0; k2 < Q; ++k2) {
-                const int x = a1 * (kp + 16 * k2);  // < A
-                const C h = tHi[x / NLO], l = tLo[x % NLO];
-                const C w = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
-                y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
+                for (int k2 = 0; k2 < Q; ++k2) {
+                    const C u = tA2[a1 * k2 * (16 / A1)];  // 16 a1 k2 / A1 < A2
+                    const C w = C{b.x * u.x - b.y * u.y, b.x * u.y + b.y * u.x};
+                    y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
+                }
+            } else {
+#pragma unroll
+                for (int k2 = 0; k2 < Q; ++k2) {
+                    const int x = a1 * (kp + 16 * k2);  // < A
+                    const C h = tHi[x / NLO], l = tLo[x % NLO];
+                    const C w = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
+                    y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
+                }
             }
         }
         __syncthreads();
@@ -412,12 +448,24 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
             if (m > 0) {
                 nm = C{(Real)0, (Real)0};
                 const int row = A2 - m;
+                if constexpr (A1 == 16) {
+                    // exp(+2 pi i a1 / 16) as immediates
+                    constexpr double c16[16] = {1, kC1, kR2, kS1, 0, -kS1, -kR2, -kC1, -1, -kC1, -kR2, -kS1, 0, kS1, kR2, kC1};
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) {
+                        const C v = xb[row * S2 + i];
+                        const Real wc = (Real)c16[i], ws = (Real)c16[(i + 12) % 16];  // sin = cos(. - pi/2)
+                        nm.x += v.x * wc - v.y * ws;
+                        nm.y += v.x * ws + v.y * wc;
+                    }
+                } else {
 #pragma unroll 4
-                for (int i = 0; i < A1; ++i) {
-                    const C v = xb[row * S2 + i];
-                    const C w = w3[i];
-                    nm.x += v.x * w.x - v.y * w.y;
-                    nm.y += v.x * w.y + v.y * w.x;
+                    for (int i = 0; i < A1; ++i) {
+                        const C v = xb[row * S2 + i];
+                        const C w = w3[i];
+                        nm.x += v.x * w.x - v.y * w.y;
+                        nm.y += v.x * w.y + v.y * w.x;
+                    }
                 }
             }
             // ring a: (X[m] + conj X[A-m]) / 2 ; ring b: (X[m] - conj X[A-m]) / (2 i)
@@ -446,14 +494,14 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
 // contiguous range of (frame, ring tile) work: tiles running together on one
 // XCD are radial neighbours and share L2 lines (a 128-byte line spans 32
 // rings where the circle runs vertically).
-template <typename Real, int A, int A2>
-__global__ __launch_bounds__((FftShape<Real, A>::NTHR)) __attribute__((amdgpu_waves_per_eu(4))) void polar_fft_kernel(
+template <typename Real, int A, int A2, int WG = 512, int TP = 8>
+__global__ __launch_bounds__((FftShape<Real, A, WG, TP>::NTHR)) __attribute__((amdgpu_waves_per_eu(4))) void polar_fft_kernel(
     FftArgs<Real> g, int gx, int G) {
-    __shared__ __attribute__((aligned(16))) char smem[FftLds<Real, A, A2>::bytes];
+    __shared__ __attribute__((aligned(16))) char smem[FftLds<Real, A, A2, WG, TP>::bytes];
     const int per_xcd = (int)(gridDim.x / 8);
     const int lid = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
     if (lid >= G) return;
-    polar_fft_tile<Real, A, A2>(g, lid / gx, lid % gx, smem);
+    polar_fft_tile<Real, A, A2, WG, TP>(g, lid / gx, lid % gx, smem);
 }
 
 }  // namespace zmk

@@ -16,12 +16,12 @@
 // are formed.  Each length-A2 DFT is a radix-16 pass in registers followed
 // by a radix-Q pass (A2 = 16 Q) after one LDS exchange.
 //
-// Work decomposition: a workgroup owns 16 consecutive rings (8 pairs) of one
-// frame and runs P pairs per round.  Each round first gathers the 2P rings
-// into LDS with a lane mapping that keeps every wave instruction on a small
-// 2-D patch of the frame (and lets the rings of the round share cache
-// lines), then A/16 threads per pair run the transform, each holding 16
-// points.  Sample angles use exact quarter-turn rotations of first-quadrant
+// Work decomposition: a workgroup owns 2P consecutive rings of one frame
+// (P = 2 at A = 4096; at least 16 rings for small A, run P pairs per round).
+// A round first gathers its 2P rings into LDS with lane maps that keep every
+// wave instruction on a small 2-D patch of the frame and every group of 4
+// lanes on neighbouring pixels of one row, then A/16 threads per pair run
+// the transform, each holding 16 points.  Sample angles use exact quarter-turn rotations of first-quadrant
 // angles.  Twiddles come from small LDS tables; the outputs go straight to
 // the ring-tile-blocked spectrum layout described at the kernel.
 #include <hip/hip_runtime.h>
@@ -32,10 +32,14 @@ namespace {
 
 using namespace zmk;
 
+constexpr int kWgSize = 512;
+
 template <typename Real, int A, int A2>
 hipError_t launch_one(const zm_plan_s* p, const void* src, long long stride, int batch, void* F, float* fmax,
                       int from_polar, hipStream_t s) {
-    using S = FftShape<Real, A>;
+    // one round of 2P rings per workgroup: the rings that share cache lines
+    // are then gathered by concurrently running workgroups
+    using S = FftShape<Real, A, kWgSize, 1>;
     const int gx = p->Rp / (2 * S::PAIRS);
     const int G = gx * batch;
     const int G8 = (G + 7) / 8 * 8;
@@ -56,7 +60,7 @@ hipError_t launch_one(const zm_plan_s* p, const void* src, long long stride, int
     g.tw = (const Real*)p->d_tw;
     g.F = (Real*)F;
     g.fmaxbuf = fmax;
-    hipLaunchKernelGGL((polar_fft_kernel<Real, A, A2>), dim3(G8), dim3(S::NTHR), 0, s, g, gx, G);
+    hipLaunchKernelGGL((polar_fft_kernel<Real, A, A2, kWgSize, 1>), dim3(G8), dim3(S::NTHR), 0, s, g, gx, G);
     return hipGetLastError();
 }
 

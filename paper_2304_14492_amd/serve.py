@@ -128,14 +128,29 @@ def run_stream(requests, scheduler: Scheduler, clock=time.perf_counter, sleep=No
     return scheduler.done
 
 
-def latency_stats(done, warmup_s: float = 0.0):
-    lat = np.array([r.t_done - r.t_arrival for r in done if r.t_arrival >= warmup_s])
-    if lat.size == 0:
-        return {}
-    span = max(r.t_done for r in done) - min(r.t_arrival for r in done)
+def _percentiles(lat):
     return dict(count=int(lat.size), p50_ms=float(np.percentile(lat, 50) * 1e3),
                 p99_ms=float(np.percentile(lat, 99) * 1e3), p999_ms=float(np.percentile(lat, 99.9) * 1e3),
-                mean_ms=float(lat.mean() * 1e3), images_per_s=float(len(done) / span) if span > 0 else 0.0)
+                mean_ms=float(lat.mean() * 1e3))
+
+
+def latency_stats(done, warmup_s: float = 0.0, by_size: bool = False):
+    """Latency percentiles over the requests that arrived after warmup_s;
+    images_per_s counts every completed request over the whole span.  With
+    by_size, also per frame size ("HxW")."""
+    kept = [r for r in done if r.t_arrival >= warmup_s]
+    if not kept:
+        return {}
+    lat = np.array([r.t_done - r.t_arrival for r in kept])
+    span = max(r.t_done for r in done) - min(r.t_arrival for r in done)
+    out = _percentiles(lat)
+    out["images_per_s"] = float(len(done) / span) if span > 0 else 0.0
+    if by_size:
+        sizes = collections.defaultdict(list)
+        for r in kept:
+            sizes[f"{r.H}x{r.W}"].append(r.t_done - r.t_arrival)
+        out["by_size"] = {k: _percentiles(np.array(v)) for k, v in sorted(sizes.items())}
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -260,13 +275,17 @@ class GpuDevice:
             self.plan(H, W, nmax)
 
 
+_FRAME_POOL: dict = {}
+
+
 def make_requests(count: int, qps: float, seed: int = 5, pool_per_size: int = 3, pin: bool = True):
     """Poisson stream (synth.request_stream); frames come from a pool of
-    `pool_per_size` seeded frames per size (request seed mod pool)."""
+    `pool_per_size` seeded frames per size (request seed mod pool), kept for
+    later calls in this process."""
     import synth
     from synth.frames import FrameSpec
     stream = synth.request_stream(count, qps, seed=seed)
-    pool = {}
+    pool = _FRAME_POOL.setdefault(pin, {})
     reqs = []
     for i, (t, H, W, nmax, fseed) in enumerate(stream):
         k = (H, W, fseed % pool_per_size)
