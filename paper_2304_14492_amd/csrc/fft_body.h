@@ -340,22 +340,40 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
             const int ri_v = tid % S::RPR;
             const double sr_v = rbase + ri_v < R ? spx[rbase + ri_v] : 0.0;
             Real* xf_v = reinterpret_cast<Real*>(xbuf + (ri_v >> 1) * XSZ) + (ri_v & 1);
+            // With NTHR / 4 a multiple of RPR the H ring of a thread is the same
+            // in every iteration, and the H angles of a wave are its V angles:
+            // the radius is loaded once and (cos, sin) is passed across lanes.
+            constexpr bool kHFixed = (NTHR / 4) % S::RPR == 0 && S::RPR <= 16;
+            const int ri_h0 = (tid >> 2) % S::RPR;
+            const double sr_h0 = rbase + ri_h0 < R ? spx[rbase + ri_h0] : 0.0;
             __syncthreads();  // previous round's phase-3 readers are done
 #pragma unroll 2
             for (int i = 0; i < 8; ++i) {
                 const int a_v = (tid + NTHR * i) / S::RPR;  // base angle, < A / 4
                 const int rest = (tid + NTHR * i) >> 2;
-                const int ri_h = rest % S::RPR;
+                const int ri_h = kHFixed ? ri_h0 : rest % S::RPR;
                 const int a_h = (rest / S::RPR) * 4 + (tid & 3);
+                const double sr_h = kHFixed ? sr_h0 : (rbase + ri_h < R ? spx[rbase + ri_h] : 0.0);
+                const double cv = trig[2 * a_v], sv = trig[2 * a_v + 1];
+                double ch, sh;
+                if constexpr (kHFixed) {
+                    // lane RPR * k of the wave holds V angle (first V angle of the wave) + k
+                    const int a_v0 = (tid - (tid & 63) + NTHR * i) / S::RPR;
+                    const int src = (tid & ~63) + S::RPR * (a_h - a_v0);
+                    ch = __shfl(cv, src & 63, 64);
+                    sh = __shfl(sv, src & 63, 64);
+                } else {
+                    ch = trig[2 * a_h];
+                    sh = trig[2 * a_h + 1];
+                }
                 // iterations 0..3 hold the base angles below A / 8 (both lane maps)
                 const bool low = i < 4;
                 // turns 0, 2 use (ring, angle) p; turns 1, 3 use q
                 const int ri_p = low ? ri_v : ri_h, a_p = low ? a_v : a_h;
                 const int ri_q = low ? ri_h : ri_v, a_q = low ? a_h : a_v;
-                const double sr_h = rbase + ri_h < R ? spx[rbase + ri_h] : 0.0;
                 const double sr_p = low ? sr_v : sr_h, sr_q = low ? sr_h : sr_v;
-                const double pc = sr_p * trig[2 * a_p], ps = sr_p * trig[2 * a_p + 1];
-                const double qc = sr_q * trig[2 * a_q], qs = sr_q * trig[2 * a_q + 1];
+                const double pc = sr_p * (low ? cv : ch), ps = sr_p * (low ? sv : sh);
+                const double qc = sr_q * (low ? ch : cv), qs = sr_q * (low ? sh : sv);
                 // the four quarter turns of (c, s): x = cx + (c, -s, -c, s), y = cy - (s, c, -s, -c);
                 // with 2 cx = W - 1 and 2 cy = H - 1 the negated offsets are mirrors
                 const Coord<Real> xa = split_coord<Real>(cx + pc), yb = split_coord<Real>(cy + ps);
