@@ -9,7 +9,9 @@ before the timed region starts.
 
 Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
   roofline       resample+FFT kernel: algorithmic bytes per launch / average
-                 launch duration (HIP events on the launch stream) vs 8 TB/s
+                 launch duration (HIP events on the launch stream) vs 8 TB/s;
+                 traffic = HBM bytes per launch from the committed rocprofv3
+                 counter summary (null once the kernel source has changed)
   projection     the projection kernel's useful FLOP rate vs the MFMA peak
   split_bf16     the same step with the hi/lo split-BF16 projection
   cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s
@@ -25,8 +27,10 @@ Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,6 +46,29 @@ DISTINCT = 4          # distinct seeded frames (seeds 3..6), tiled to fill the b
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0}
 METRIC = "4K images/s at N_max=200 (FP32 vs split-BF16) + p50/p99 latency at fixed QPS"
+
+
+# HBM bytes of the resample+FFT kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters (scaled by a copy of known size), as committed with the counter
+# summary; used only while the kernel sources are the ones it was taken on.
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "polar_fft_kernel_4k_n200_b64.md")
+COUNTER_BATCH = 64
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_14492_amd", "csrc", f) for f in ("fft_body.h", "polar_fft.hip")]
+
+
+def measured_traffic(batch):
+    try:
+        txt = open(COUNTER_SUMMARY).read()
+        h = hashlib.sha256()
+        for f in KERNEL_SOURCES:
+            h.update(open(f, "rb").read())
+    except OSError:
+        return None
+    t = re.search(r"traffic-bytes-per-launch: (\d+)", txt)
+    k = re.search(r"kernel-source-sha256: ([0-9a-f]{64})", txt)
+    if not (t and k) or k.group(1) != h.hexdigest() or batch != COUNTER_BATCH:
+        return None
+    return int(t.group(1))
 
 
 def disk_pixels(h, w):
@@ -131,7 +158,7 @@ def cpu_baseline(budget_s):
         oracle.moments(f, NMAX, RINGS, ANGLES, plist=pl, table=table)
         n += 1
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 50:
+        if el >= budget_s or n >= 200:
             break
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return dict(value=n / el, unit="images/s", cores=min(cores, os.cpu_count() or cores), kind="oracle",
@@ -269,7 +296,7 @@ def main():
                    "projection": args.dtype},
         "roofline": {"bound": "hbm", "kernel": "polar_fft_kernel (fused resample + angular FFT)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.batch),
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": round(r["spec_ms"], 4)},
         "projection": {"kernel": "project_kernel", "avg_launch_ms": round(r["proj_ms"], 4),
                        "useful_tflops": round(proj_tflops, 2), "peak_tflops": MFMA_PEAK_TFLOPS[args.dtype],
