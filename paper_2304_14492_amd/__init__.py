@@ -26,6 +26,11 @@ if not os.path.exists(LIB_PATH):
         f"libzm.so is not built ({LIB_PATH}); run `python -c 'import __graft_entry__ as g; g.build()'` "
         "or `python paper_2304_14492_amd/_build.py` first")
 
+# torch first: its HIP runtime is then the one libzm binds to, so the
+# library, torch's allocator and torch's streams share one runtime in the
+# process (loading libzm first pulls in the system runtime instead).
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 ZM_OK, ZM_EINVAL, ZM_ENOMEM, ZM_EDEVICE, ZM_EUNSUPPORTED, ZM_EBUSY = 0, -1, -2, -3, -4, -5

@@ -44,8 +44,12 @@ constexpr int kA2List[5] = {16, 32, 64, 128, 256};
 // (512-thread shape), LDS within the batch kernel's budget
 template <int A, int A2>
 constexpr bool batch_variant_ok() {
-    return A2 * 2 <= A && FftLds<float, A, A2>::bytes <= 90 * 1024;
+    return A2 * 2 <= A && FftLds<float, A, A2>::bytes <= 80 * 1024;  // two workgroups per CU
 }
+
+// a stage-1 item covers max(kItemPairs, P) ring pairs of one frame (several
+// rounds of the FFT body when P < kItemPairs)
+constexpr int kItemPairs = 8;
 
 template <int AI, int A2I>
 constexpr size_t lds_of() {
@@ -89,7 +93,7 @@ __shared__ __attribute__((aligned(16))) char g_batch_smem[kBatchLds];
 template <int AI, int A2I>
 __device__ __attribute__((noinline)) void run_tile(const BatchJob* j, int tile) {
     if constexpr (batch_variant_ok<kAList[AI], kA2List[A2I]>())
-        polar_fft_tile<float, kAList[AI], kA2List[A2I]>(j->fa, 0, tile, g_batch_smem);
+        polar_fft_tile<float, kAList[AI], kA2List[A2I], 512, kItemPairs>(j->fa, 0, tile, g_batch_smem);
 }
 
 template <int AI>
@@ -194,7 +198,15 @@ bool variant_ok(int ai, int a2i) {
         {host_ok<3, 0>(), host_ok<3, 1>(), host_ok<3, 2>(), host_ok<3, 3>(), host_ok<3, 4>()}};
     return ai >= 0 && a2i >= 0 && tab[ai][a2i];
 }
-int pairs_of(int A) { return A == 512 ? 16 : 8; }  // FftShape<float, A>::PAIRS for A >= 512
+// ring pairs per stage-1 item: FftShape<float, A, 512, kItemPairs>::PAIRS
+int pairs_of(int A) {
+    switch (A) {
+        case 512: return FftShape<float, 512, 512, kItemPairs>::PAIRS;
+        case 1024: return FftShape<float, 1024, 512, kItemPairs>::PAIRS;
+        case 2048: return FftShape<float, 2048, 512, kItemPairs>::PAIRS;
+        default: return FftShape<float, 4096, 512, kItemPairs>::PAIRS;
+    }
+}
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 

@@ -237,7 +237,9 @@ struct FftLds {
     static constexpr int Q = A2 / 16;
     static constexpr int KG = 16 / Q;
     static constexpr int S1 = NT + pad_s1(NT, KG, A1);
-    static constexpr int S2 = A1 + 1;
+    // second exchange row stride: padded against bank conflicts, except for
+    // A1 <= 4, where the padding would cost 25 % or more of the buffer
+    static constexpr int S2 = A1 <= 4 ? A1 : A1 + 1;
     static constexpr int XSZ0 = (16 * S1 > A2 * S2) ? 16 * S1 : A2 * S2;
     static constexpr int XSZ1 = XSZ0 > A ? XSZ0 : A;  // also holds the A gathered samples of a pair
     // pair slots are 32/P complex (mod 32) apart, so the gather's lanes
