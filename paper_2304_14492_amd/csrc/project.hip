@@ -49,9 +49,16 @@ ProjArgs make_proj_args(const zm_plan_s* p, const void* F, const float* fmax, in
     return a;
 }
 
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
+// XCD runs a contiguous range of units.  Units are ordered by m, so the
+// row blocks of one m (which all read the same spectra slice F[., m, ., .])
+// then share one L2 and the slice comes from HBM once.
 template <int DT>
-__global__ __launch_bounds__(64 * kWaves) void project_kernel(ProjArgs a) {
-    const int unit = blockIdx.x * kWaves + (threadIdx.x >> 6);
+__global__ __launch_bounds__(64 * kWaves) void project_kernel(ProjArgs a, int n_blocks) {
+    const int per_xcd = (int)(gridDim.x / 8);
+    const int blk = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    if (blk >= n_blocks) return;
+    const int unit = blk * kWaves + (threadIdx.x >> 6);
     if (unit >= a.n_units) return;
     project_unit<DT>(a, unit, threadIdx.x & 63);
 }
@@ -60,7 +67,8 @@ template <int DT>
 hipError_t launch_dt(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
     ProjArgs a = make_proj_args(p, F, fmax, batch, Z, nullptr);
     const int blocks = (a.n_units + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL((project_kernel<DT>), dim3(blocks), dim3(64 * kWaves), 0, s, a);
+    const int blocks8 = (blocks + 7) / 8 * 8;
+    hipLaunchKernelGGL((project_kernel<DT>), dim3(blocks8), dim3(64 * kWaves), 0, s, a, blocks);
     return hipGetLastError();
 }
 
