@@ -16,7 +16,8 @@ Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
   split_bf16     the same step with the hi/lo split-BF16 projection
   cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s
   batch_form     64 mixed square frames (sides 256..2048, N_max 30/50/100) in
-                 one persistent launch replayed from a HIP graph
+                 one persistent launch replayed from a HIP graph; beside it the
+                 same frames as per-plan zm_moments launches
   latency        the serving form: Poisson arrivals at a fixed rate of
                  640x480 / 1080p / 4K frames (N_max 30/100/200) from pinned host
                  memory, continuous batching under an HBM budget; p50 / p99 /
@@ -191,8 +192,27 @@ def batch_form(steps):
     ms = e0.elapsed_time(e1) / steps
     cfg = b.config()
     b.close()
+    # reference: the same frames as one zm_moments launch pair per plan (frames of
+    # a plan stacked), back to back on one stream
+    groups = {}
+    for (side, nmax, _), f in zip(specs, frames):
+        groups.setdefault((side, nmax), []).append(f)
+    stacks = [(cache[k], torch.stack(v)) for k, v in groups.items()]
+    outs = [(pl, st, pl.workspace(st.shape[0]), torch.empty(st.shape[0], pl.num_moments, 2, device="cuda"))
+            for pl, st in stacks]
+    for pl, st, ws, z in outs:
+        pl.moments(st, out=z, workspace=ws)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        for pl, st, ws, z in outs:
+            pl.moments(st, out=z, workspace=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_plan = e0.elapsed_time(e1) / steps
     return {"images_per_s": round(len(frames) / (ms / 1e3), 1), "ms_per_batch": round(ms, 4), "frames": len(frames),
-            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "queue_items": cfg["n_items"]}
+            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "queue_items": cfg["n_items"],
+            "per_plan_launches_ms": round(ms_plan, 4)}
 
 
 def serving(dtype, count, qps, warmup_s):
