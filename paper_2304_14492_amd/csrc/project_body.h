@@ -126,13 +126,25 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
         const float* T = (const float*)thi;
         const float* F = (const float*)Fv;
         floatx4 acc[2][2] = {};
-        for (int k0 = 0; k0 < Rp; k0 += 16) {
+        // operand fragments run two ring steps ahead of the MFMAs (Rp is a multiple of 32)
+        float4 a1[2], b1[2], a2[2], b2[2];
+        auto load = [&](int k0, float4* a, float4* b) {
             const int kk = k0 + 4 * lg;
-            float4 a[2], b[2];
             a[0] = *(const float4*)(T + aoff[0] + kk);
-            if (two) a[1] = *(const float4*)(T + aoff[1] + kk);
+            a[1] = two ? *(const float4*)(T + aoff[1] + kk) : float4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < 2; ++u) b[u] = *(const float4*)(F + boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg);
+        };
+        load(0, a1, b1);
+        load(16, a2, b2);
+        for (int k0 = 0; k0 < Rp; k0 += 16) {
+            const float4 a[2] = {a1[0], a1[1]}, b[2] = {b1[0], b1[1]};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                a1[u] = a2[u];
+                b1[u] = b2[u];
+            }
+            if (k0 + 32 < Rp) load(k0 + 32, a2, b2);
             const float av[2][4] = {{a[0].x, a[0].y, a[0].z, a[0].w}, {a[1].x, a[1].y, a[1].z, a[1].w}};
             const float bv[2][4] = {{b[0].x, b[0].y, b[0].z, b[0].w}, {b[1].x, b[1].y, b[1].z, b[1].w}};
 #pragma unroll
@@ -171,20 +183,39 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
             for (int u = 0; u < 2; ++u) fsc[u] = f16_frame_scale(fmaxbuf[fr[u] < B ? fr[u] : B - 1]);
         }
         floatx4 acc[2][2] = {};
-        for (int k0 = 0; k0 < Rp; k0 += 32) {
+        // raw operand fragments of ring step k0 + 32 are loaded while step k0 runs
+        H8 nah[2] = {}, nal[2] = {};
+        float4 ny[2][2];
+        auto load = [&](int k0) {
             const int kk = k0 + 8 * lg;
-            H8 ah[2], al[2], bh[2], bl[2];
-            ah[0] = *(const H8*)(Th + aoff[0] + kk);
-            al[0] = *(const H8*)(Tl + aoff[0] + kk);
+            nah[0] = *(const H8*)(Th + aoff[0] + kk);
+            nal[0] = *(const H8*)(Tl + aoff[0] + kk);
             if (two) {
-                ah[1] = *(const H8*)(Th + aoff[1] + kk);
-                al[1] = *(const H8*)(Tl + aoff[1] + kk);
+                nah[1] = *(const H8*)(Th + aoff[1] + kk);
+                nal[1] = *(const H8*)(Tl + aoff[1] + kk);
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const size_t fo = boff[u] + (size_t)((k0 >> 4) + (lg >> 1)) * TS + 8 * (lg & 1);
-                const float4 y0 = *(const float4*)(F + fo);
-                const float4 y1 = *(const float4*)(F + fo + 4);
+                ny[u][0] = *(const float4*)(F + fo);
+                ny[u][1] = *(const float4*)(F + fo + 4);
+            }
+        };
+        load(0);
+        for (int k0 = 0; k0 < Rp; k0 += 32) {
+            H8 ah[2], al[2], bh[2], bl[2];
+            float4 yy[2][2];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                ah[s2] = nah[s2];
+                al[s2] = nal[s2];
+                yy[s2][0] = ny[s2][0];
+                yy[s2][1] = ny[s2][1];
+            }
+            if (k0 + 32 < Rp) load(k0 + 32);
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const float4 y0 = yy[u][0], y1 = yy[u][1];
                 const float yv[8] = {y0.x, y0.y, y0.z, y0.w, y1.x, y1.y, y1.z, y1.w};
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
