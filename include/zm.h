@@ -108,8 +108,10 @@ zm_status zm_plan(int n_max, int H, int W, zm_dtype dtype, int neumann, zm_plan_
 
 /* As zm_plan with an explicit descriptor (R, A, ring rule, device).
  * Constraints: 1 <= R <= 4096; A a power of two with 32 <= A <= 4096 and
- * A >= 2 n_max + 2.  n_max > 255 plans only serve zm_radial_table
- * (zm_moments then returns ZM_EUNSUPPORTED). */
+ * A >= 2 n_max + 2.  For plans with n_max > 255, or ZM_F64 plans with
+ * A > 1024, the moment entry points (zm_moments, zm_spectra, zm_project,
+ * zm_moments_polar, the batch calls) return ZM_EUNSUPPORTED; the table,
+ * ring-node and reconstruction entry points serve them. */
 zm_status zm_plan_ex(const zm_plan_desc* desc, zm_plan_t* out);
 
 zm_status zm_plan_info(zm_plan_t plan, zm_plan_info_t* out);
