@@ -179,6 +179,25 @@ def test_ragged_geometries(zm, H, W, nmax, R, A, dtype):
     assert e <= (1e-11 if dtype == "f64" else 1e-5), e
 
 
+@pytest.mark.parametrize("H,W,nmax,R,A,dtype", [
+    (64, 64, 0, 32, 32, "f32"),      # n_max = 0: the single moment Z_00
+    (64, 64, 5, 1, 32, "f32"),       # one ring
+    (2, 2, 0, 1, 32, "f64"),         # smallest frame (disk radius one pixel)
+    (2, 3, 3, 1, 32, "f32"),         # smallest non-square frame
+    (260, 260, 255, 130, 512, "f32"),  # the largest order the moment kernels serve
+])
+def test_degenerate_plans(zm, H, W, nmax, R, A, dtype):
+    f = synth.make_frame(synth.FrameSpec(H, W, blobs=3, polygons=1, zero_outside=False, dtype="float64"),
+                         seed=7 * H + W)
+    fin = f if dtype == "f64" else f.astype(np.float32)
+    Zo = oracle.moments(fin.astype(np.float64), nmax, R, A)
+    plan = zm.Plan(nmax, H, W, dtype=dtype, rings=R, angles=A)
+    Z = gpu_moments(zm, plan, fin[None])[0]
+    assert Z.shape == Zo.shape == (zm.num_moments(nmax),)
+    e = rel_l2(Z, Zo)
+    assert e <= (1e-11 if dtype == "f64" else 1e-5), e
+
+
 def test_gauss_legendre_moments(zm):
     f = synth.config_frame(2)
     Zo = oracle.moments(f.astype(np.float64), 60, 62, 256, rule="gauss_legendre")
