@@ -457,7 +457,7 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         members[gid[p]].push_back(i);
     }
     b->ngroups = (int)members.size();
-    ZM_HIP(hipSetDevice(b->device));
+    ZM_DEVICE(b->device);
     // workspace layout: per group [F of its frames][F16 max slots]; counters
     std::vector<size_t> foff(b->ngroups);
     size_t fbytes = 0;
@@ -583,14 +583,14 @@ zm_status zm_batch_update(zm_batch_t b, const zm_job* jobs, int njobs) {
         if (jobs[i].plan != b->plans[i]) return fail(ZM_EINVAL, "jobs must keep their plans and order");
     zm_status st = fill_pointers(b, jobs);
     if (st != ZM_OK) return st;
-    ZM_HIP(hipSetDevice(b->device));
+    ZM_DEVICE(b->device);
     ZM_HIP(hipDeviceSynchronize());  // descriptors may be in use by a running replay
     return upload(b);
 }
 
 zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
     if (!b) return fail(ZM_EINVAL, "null batch");
-    ZM_HIP(hipSetDevice(b->device));
+    ZM_DEVICE(b->device);
     hipStream_t s = (hipStream_t)stream;
     if (b->exec) {
         ZM_HIP(hipGraphLaunch(b->exec, s));
@@ -603,7 +603,7 @@ zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
 
 zm_status zm_batch_check(zm_batch_t b) {
     if (!b) return fail(ZM_EINVAL, "null batch");
-    ZM_HIP(hipSetDevice(b->device));
+    ZM_DEVICE(b->device);
     ZM_HIP(hipDeviceSynchronize());
     return check_error_flag(b);
 }
@@ -619,7 +619,7 @@ zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* n_items, siz
 
 zm_status zm_batch_destroy(zm_batch_t b) {
     if (!b) return fail(ZM_EINVAL, "null batch");
-    (void)hipSetDevice(b->device);
+    zm::DeviceGuard guard(b->device);
     (void)hipDeviceSynchronize();
     destroy_batch(b);
     return ZM_OK;

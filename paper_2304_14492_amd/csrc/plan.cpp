@@ -193,8 +193,8 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
         int cnt = 0;
         ZM_HIP(hipGetDeviceCount(&cnt));
         if (dev >= cnt) return fail(ZM_EINVAL, "device ordinal out of range");
-        ZM_HIP(hipSetDevice(dev));
     }
+    ZM_DEVICE(dev);
 
     zm_plan_s* p = new zm_plan_s();
     p->n_max = d->n_max;
@@ -398,7 +398,7 @@ zm_status zm_radial_table(zm_plan_t p, double* host_out, size_t n_elems) {
     if (!p || !host_out) return fail(ZM_EINVAL, "null plan or output");
     const size_t need = (size_t)p->num_moments * p->R;
     if (n_elems < need) return fail(ZM_EINVAL, "output too small: need num_moments * rings elements");
-    ZM_HIP(hipSetDevice(p->device));
+    ZM_DEVICE(p->device);
     ZM_HIP(hipMemcpy(host_out, p->d_table, need * sizeof(double), hipMemcpyDeviceToHost));
     return ZM_OK;
 }
@@ -440,6 +440,7 @@ static zm_status run_spectra(zm_plan_t p, const void* src, int batch, long long 
     zm_status st = check_run(p, batch, d_ws, ws_bytes);
     if (st != ZM_OK || batch == 0) return st;
     if (!src) return fail(ZM_EINVAL, "null input pointer");
+    ZM_DEVICE(p->device);
     hipStream_t s = (hipStream_t)stream;
     float* fmax = fmax_slot(p, d_ws, batch);
     if (fmax) {
@@ -462,6 +463,7 @@ zm_status zm_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_by
     zm_status st = check_run(p, batch, d_ws, ws_bytes);
     if (st != ZM_OK || batch == 0) return st;
     if (!d_Z) return fail(ZM_EINVAL, "null output pointer");
+    ZM_DEVICE(p->device);
     hipError_t e = launch_project(p, d_ws, fmax_slot(p, d_ws, batch), batch, d_Z, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
     return ZM_OK;
@@ -502,16 +504,19 @@ zm_status zm_reconstruct(zm_plan_t p, const void* d_Z, int batch, void* d_out, i
         return fail(ZM_EINVAL, "ZM_RECON_MINMAX applies to Cartesian reconstructions");
     if (batch == 0) return ZM_OK;
     if (!d_Z || !d_out) return fail(ZM_EINVAL, "null device pointer");
+    if (flags & ZM_RECON_MINMAX) {
+        size_t need = 0;
+        zm_recon_workspace_size(p, batch, &need);
+        if (!d_ref || !d_ws || ws_bytes < need)
+            return fail(ZM_EINVAL, "ZM_RECON_MINMAX needs d_ref and a workspace of zm_recon_workspace_size bytes");
+    }
+    ZM_DEVICE(p->device);
     hipStream_t s = (hipStream_t)stream;
     const int one = (flags & ZM_RECON_ONESIDED) ? 1 : 0;
     hipError_t e = kind == ZM_RECON_POLAR ? launch_recon_polar(p, d_Z, batch, d_out, one, s)
                                           : launch_recon_cart(p, d_Z, batch, d_out, one, s);
     if (e != hipSuccess) return hip_fail(e, "reconstruction kernel launch");
     if (flags & ZM_RECON_MINMAX) {
-        size_t need = 0;
-        zm_recon_workspace_size(p, batch, &need);
-        if (!d_ref || !d_ws || ws_bytes < need)
-            return fail(ZM_EINVAL, "ZM_RECON_MINMAX needs d_ref and a workspace of zm_recon_workspace_size bytes");
         double* part = (double*)d_ws;
         double* mm = (double*)((char*)d_ws + align256((size_t)batch * recon_reduce_blocks(p) * 4 * sizeof(double)));
         e = launch_minmax(p, d_ref, d_out, batch, part, mm, s);
@@ -529,6 +534,7 @@ zm_status zm_recon_error(zm_plan_t p, const void* d_ref, const void* d_recon, in
     zm_recon_workspace_size(p, batch, &need);
     if (!d_ref || !d_recon || !host_out || !d_ws || ws_bytes < need)
         return fail(ZM_EINVAL, "null pointer or workspace smaller than zm_recon_workspace_size");
+    ZM_DEVICE(p->device);
     hipStream_t s = (hipStream_t)stream;
     double* part = (double*)d_ws;
     double* out = (double*)((char*)d_ws + align256((size_t)batch * recon_reduce_blocks(p) * 4 * sizeof(double)));
@@ -570,7 +576,7 @@ zm_status zm_embed(const void* d_src, int n, int batch, void* d_dst, int is_doub
 
 zm_status zm_destroy(zm_plan_t p) {
     if (!p) return fail(ZM_EINVAL, "null plan");
-    (void)hipSetDevice(p->device);
+    zm::DeviceGuard guard(p->device);  // frees on the plan's device even if selecting it failed
     free_plan(p);
     return ZM_OK;
 }

@@ -23,6 +23,27 @@ zm_status hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return zm::hip_fail(e_, #call); \
     } while (0)
 
+// Makes `dev` the current HIP device for the scope and restores the
+// caller's device on exit (entry points run on their plan's device without
+// changing the caller's state).
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        if (prev >= 0 && err == hipSuccess) (void)hipSetDevice(prev);
+    }
+    DeviceGuard(const DeviceGuard&) = delete;
+    DeviceGuard& operator=(const DeviceGuard&) = delete;
+};
+
+#define ZM_DEVICE(dev)                                             \
+    zm::DeviceGuard zm_device_guard_(dev);                         \
+    if (zm_device_guard_.err != hipSuccess) return zm::hip_fail(zm_device_guard_.err, "hipSetDevice")
+
 // Largest order the moment kernels serve (the pruned FFT keeps bins
 // 0..n_max inside one sub-transform of at most 256 points).
 constexpr int kMaxMomentOrder = 255;
