@@ -4,12 +4,16 @@
 // The host groups the jobs by plan and builds a device work queue:
 //   stage-1 items (frame, ring tile)      -> fused resample + ring FFT,
 //   stage-2 items (plan group, 8 blocks)  -> radial projection on MFMA.
-// One persistent kernel pops items with an atomic counter.  A finished
-// stage-1 tile releases its writes (device-scope fence) and bumps its group's
-// counter; a stage-2 item waits (acquire) until its group's counter reaches
-// the group's tile count.  Every stage-1 item is popped before any stage-2
-// item (queue order), and stage-1 items never wait, so every wait ends; the
-// wait is bounded anyway and reports an error flag if the bound trips.
+// One persistent kernel pops items with atomic counters: stage-1 items from
+// eight ranges (one per XCD, taking from the others when its own is empty),
+// then stage-2 items.  A workgroup counts its finished stage-1 tiles and,
+// when it moves on to another group, to stage 2 or to the exit, releases
+// them (device-scope release fence) and adds them to the group's counter; a
+// stage-2 item waits (acquire) until its group's counter reaches the group's
+// tile count.  Every stage-1 item is popped before any stage-2 item, stage-1
+// items never wait, and a workgroup releases before it takes a stage-2 item,
+// so every wait ends; the wait is bounded anyway and reports an error flag
+// if the bound trips.
 // Each item runs exactly the code of the standalone kernels, so a frame's
 // moments are bit-identical alone and in a batch.
 //
@@ -49,7 +53,7 @@ constexpr bool batch_variant_ok() {
 
 // a stage-1 item covers max(kItemPairs, P) ring pairs of one frame (several
 // rounds of the FFT body when P < kItemPairs)
-constexpr int kItemPairs = 8;
+constexpr int kItemPairs = 1;
 
 template <int AI, int A2I>
 constexpr size_t lds_of() {
@@ -81,19 +85,68 @@ struct BatchItem {
     int kind;  // 0: stage-1 (job, tile), 1: stage-2 (group, block of 8 units)
     int idx;
     int sub;
-    int pad;
+    int group;  // stage-1: the job's plan group; stage-2: -1
 };
 
-// LDS of the persistent kernel, shared by all item bodies.  Each variant
-// body is a separate (non-inlined) function so that it gets its own register
-// allocation; it addresses this array directly, so its LDS accesses stay
-// LDS instructions.
+
+// Reads *p with scalar loads: the address is made wave-uniform and the read
+// goes through the constant address space (the tables are written by the
+// host before the launch and only read by the kernel).
+template <class T>
+__device__ __forceinline__ T uniform_load(const T* p) {
+    using CU = const __attribute__((address_space(4))) unsigned;
+    const unsigned long long a = (unsigned long long)p;
+    CU* q = (CU*)(((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(a >> 32)) << 32) |
+                  (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((unsigned)a));
+    static_assert(sizeof(T) % 4 == 0, "");
+    T out;
+    unsigned* o = reinterpret_cast<unsigned*>(&out);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) o[k] = q[k];
+    return out;
+}
+
+// Reads the pointer field *f (in a table of the kernel's) as a pointer to
+// global memory, with a scalar load, and returns it as a generic pointer.
+// The compiler's address-space inference then makes the accesses through it
+// global loads and stores, as for a kernel argument, instead of flat ones
+// (which need a 64-bit address per lane and wait on the LDS counter too).
+template <class T>
+__device__ __forceinline__ T* global_field(T* const* f) {
+    using GP = __attribute__((address_space(1))) T*;
+    const unsigned long long a = (unsigned long long)f;
+    const __attribute__((address_space(4))) GP* q =
+        (const __attribute__((address_space(4))) GP*)(((unsigned long long)__builtin_amdgcn_readfirstlane(
+                                                            (unsigned)(a >> 32))
+                                                        << 32) |
+                                                       (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                                           (unsigned)a));
+    return (T*)*q;
+}
+
+// LDS of the persistent kernel, shared by all item bodies.
 __shared__ __attribute__((aligned(16))) char g_batch_smem[kBatchLds];
 
+// Each item body is a separate (non-inlined) function, so that the register
+// pressure of one variant does not add to another's.  It reads its job's
+// arguments with scalar loads and marks their pointers as global memory, so
+// its code matches the standalone kernel's (which gets both from being a
+// kernel); the kernel's occupancy target (4 waves per SIMD, two 512-thread
+// workgroups per CU, what the LDS allows anyway) bounds every body's
+// registers.
 template <int AI, int A2I>
 __device__ __attribute__((noinline)) void run_tile(const BatchJob* j, int tile) {
-    if constexpr (batch_variant_ok<kAList[AI], kA2List[A2I]>())
-        polar_fft_tile<float, kAList[AI], kA2List[A2I], 512, kItemPairs>(j->fa, 0, tile, g_batch_smem);
+    if constexpr (batch_variant_ok<kAList[AI], kA2List[A2I]>()) {
+        FftArgs<float> fa = uniform_load(&j->fa);
+        fa.src = global_field(&j->fa.src);
+        fa.spx = global_field(&j->fa.spx);
+        fa.trig = global_field(&j->fa.trig);
+        fa.tw = global_field(&j->fa.tw);
+        fa.F = global_field(&j->fa.F);
+        fa.fmaxbuf = global_field(&j->fa.fmaxbuf);
+        tile = __builtin_amdgcn_readfirstlane(tile);
+        polar_fft_tile<float, kAList[AI], kA2List[A2I], 512, kItemPairs>(fa, 0, tile, g_batch_smem);
+    }
 }
 
 template <int AI>
@@ -110,7 +163,17 @@ __device__ __forceinline__ void run_tile_a2(const BatchJob* j, int a2i, int tile
 
 template <int DT>
 __device__ __attribute__((noinline)) void run_proj(const BatchGroup* g, int unit, int lane) {
-    project_unit<DT>(g->pa, unit, lane);
+    ProjArgs pa = uniform_load(&g->pa);
+    pa.items = global_field(&g->pa.items);
+    pa.thi = global_field(&g->pa.thi);
+    pa.tlo = global_field(&g->pa.tlo);
+    pa.rowscale = global_field(&g->pa.rowscale);
+    pa.F = global_field(&g->pa.F);
+    pa.fmaxbuf = global_field(&g->pa.fmaxbuf);
+    pa.Z = global_field(&g->pa.Z);
+    pa.Zptrs = global_field(&g->pa.Zptrs);
+    unit = __builtin_amdgcn_readfirstlane(unit);
+    project_unit<DT>(pa, unit, lane);
 }
 
 __global__ void batch_reset_kernel(unsigned* p, int n) {
@@ -118,20 +181,80 @@ __global__ void batch_reset_kernel(unsigned* p, int n) {
     if (i < n) p[i] = 0u;
 }
 
-// ctr[0] = queue head, ctr[1 + g] = finished tiles of group g,
-// ctr[1 + n_groups] = error flag (a wait that hit its bound)
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchItem* __restrict__ items, int n_items,
+// Queues: stage-1 items sit in kQueues contiguous ranges, one per XCD (a
+// range holds whole frames in radial order, so rings that share cache lines
+// are gathered in one L2); stage-2 items follow in one range.
+constexpr int kQueues = 8;
+struct QueueInfo {
+    int off[kQueues + 1];  // first item of each stage-1 range, then of stage 2
+    int len[kQueues + 1];
+};
+// ctr[q] = head of range q (q <= kQueues), ctr[kQueues + 1 + g] = finished
+// tiles of group g, ctr[kQueues + 1 + n_groups] = error flag (a wait that hit
+// its bound)
+constexpr int kCtrGroups = kQueues + 1;
+
+// Next item for a workgroup whose home range is `home` (thread 0 only): its
+// own range first, then the other stage-1 ranges, then stage 2.  Heads only
+// grow, so stage-2 items are taken only after every stage-1 item has been
+// taken, and a workgroup waiting in stage 2 holds no stage-1 item.
+__device__ __forceinline__ int pop_item(const QueueInfo& q, unsigned* ctr, int home) {
+    for (int d = 0; d < kQueues; ++d) {
+        const int r = (home + d) % kQueues;
+        if (__hip_atomic_load(&ctr[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)q.len[r]) {
+            const unsigned k = atomicAdd(&ctr[r], 1u);
+            if (k < (unsigned)q.len[r]) return q.off[r] + (int)k;
+        }
+    }
+    const unsigned k = atomicAdd(&ctr[kQueues], 1u);
+    return k < (unsigned)q.len[kQueues] ? q.off[kQueues] + (int)k : -1;
+}
+
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4))) void batch_kernel(const BatchItem* __restrict__ items, QueueInfo q,
                                                               const BatchJob* __restrict__ jobs,
                                                               const BatchGroup* __restrict__ groups, int n_groups,
                                                               unsigned* ctr, unsigned spin_limit) {
     __shared__ int cur;
     const int tid = threadIdx.x;
+    // workgroups are dealt round-robin to the XCDs
+    const int home = (int)(blockIdx.x % kQueues);
+    // Thread 0 takes the next item one ahead, so the atomics' latency
+    // overlaps the current item.  It also holds the workgroup's finished
+    // tiles that are not yet released (`pend` tiles of group `pend_group`).
+    // A release writes the XCD's L2 back, which stalls the gathers of every
+    // workgroup on that XCD, so it is done once per run of tiles of one
+    // group: when the next item is of another group, a stage-2 item (which
+    // may wait) or none.  No stage-2 item is popped while stage-1 items
+    // remain, and a workgroup releases before it takes one, so every wait
+    // still ends.
+    int next = 0, next_group = -1, pend_group = -1;
+    unsigned pend = 0;
+    if (tid == 0) {
+        next = pop_item(q, ctr, home);
+        if (next >= 0) next_group = items[next].group;
+    }
     for (;;) {
-        __syncthreads();  // previous item's LDS users are done; `cur` is free
-        if (tid == 0) cur = (int)atomicAdd(&ctr[0], 1u);
+        // previous item's LDS users are done and all its waves' stores have
+        // completed (each waited for them); `cur` is free
         __syncthreads();
-        const int i = cur;
-        if (i >= n_items) return;
+        if (tid == 0) {
+            if (pend && next_group != pend_group) {
+                // device-scope release of the workgroup's tiles: writes the
+                // L2's dirty lines back (a release fence does not invalidate,
+                // so the XCD keeps the frame lines other workgroups gather)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                atomicAdd(&ctr[kCtrGroups + pend_group], pend);
+                pend = 0;
+            }
+            cur = next;
+            if (next >= 0) {
+                next = pop_item(q, ctr, home);
+                next_group = next >= 0 ? items[next].group : -1;
+            }
+        }
+        __syncthreads();
+        const int i = __builtin_amdgcn_readfirstlane(cur);  // uniform: scalar loads of the item and its job
+        if (i < 0) return;
         const BatchItem it = items[i];
         if (it.kind == 0) {
             const BatchJob* j = jobs + it.idx;
@@ -144,24 +267,32 @@ __global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchItem* _
                 case 3: run_tile_a2<3>(j, a2i, it.sub); break;
                 default: break;
             }
-            __threadfence();  // release this tile's spectra (device scope)
-            __syncthreads();
-            if (tid == 0) atomicAdd(&ctr[1 + j->group], 1u);
+            // this wave's spectra stores have reached the L2 before the
+            // barrier that precedes thread 0's release
+            __builtin_amdgcn_s_waitcnt(0);
+            if (tid == 0) {
+                pend_group = it.group;
+                ++pend;
+            }
         } else {
             const BatchGroup* g = groups + it.idx;
             const unsigned need = g->tiles_total;
             if (tid == 0) {
                 unsigned spins = 0;
-                while (__hip_atomic_load(&ctr[1 + it.idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                while (__hip_atomic_load(&ctr[kCtrGroups + it.idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                       need) {
                     __builtin_amdgcn_s_sleep(8);
                     if (++spins > spin_limit) {
-                        atomicOr(&ctr[1 + n_groups], 1u);
+                        atomicOr(&ctr[kCtrGroups + n_groups], 1u);
                         break;
                     }
                 }
+                // Acquire the group's spectra: invalidates this CU's vector
+                // cache and the XCD's L2, which every wave of the workgroup
+                // reads through; the barrier below orders their loads after it.
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
-            __threadfence();  // acquire the group's spectra
             const int unit = it.sub * (kBatchThreads / 64) + (tid >> 6);
             if (unit < g->pa.n_units) {
                 switch (g->dtype) {
@@ -222,6 +353,7 @@ struct zm_batch_s {
     std::vector<BatchItem> stage1, stage2;  // natural order
     std::vector<std::vector<void*>> zptrs;  // per group
     int n_items = 0;
+    QueueInfo qinfo{};
     int grid = 0;
     int order = 0;  // 0: cost-descending stage 1, 1: natural
     // device memory
@@ -251,6 +383,23 @@ zm_status upload(zm_batch_s* b) {
             return (long)px->A * pairs_of(px->A) > (long)py->A * pairs_of(py->A);
         });
     }
+    // split stage 1 into kQueues contiguous ranges of about equal cost (samples per item)
+    auto cost = [&](const BatchItem& x) {
+        const zm_plan_s* px = b->plans[x.idx];
+        return (double)px->A * pairs_of(px->A);
+    };
+    double total = 0.0;
+    for (const BatchItem& x : s1) total += cost(x);
+    size_t pos = 0;
+    double acc = 0.0;
+    for (int r = 0; r < kQueues; ++r) {
+        b->qinfo.off[r] = (int)pos;
+        const double target = total * (r + 1) / kQueues;
+        while (pos < s1.size() && (r == kQueues - 1 || acc + 0.5 * cost(s1[pos]) < target)) acc += cost(s1[pos++]);
+        b->qinfo.len[r] = (int)pos - b->qinfo.off[r];
+    }
+    b->qinfo.off[kQueues] = (int)s1.size();
+    b->qinfo.len[kQueues] = (int)b->stage2.size();
     items.insert(items.end(), s1.begin(), s1.end());
     items.insert(items.end(), b->stage2.begin(), b->stage2.end());
     b->n_items = (int)items.size();
@@ -267,7 +416,7 @@ hipError_t enqueue(zm_batch_s* b, hipStream_t s) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((b->n_zero + 255) / 256), dim3(256), 0, s, b->d_zero, b->n_zero);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(batch_kernel, dim3(b->grid), dim3(kBatchThreads), 0, s, b->d_items, b->n_items, b->d_jobs,
+    hipLaunchKernelGGL(batch_kernel, dim3(b->grid), dim3(kBatchThreads), 0, s, b->d_items, b->qinfo, b->d_jobs,
                        b->d_groups, b->ngroups, b->d_zero, b->spin_limit);
     return hipGetLastError();
 }
@@ -344,7 +493,7 @@ void tune_cache_store(const std::string& sig, int grid, int order) {
 
 zm_status check_error_flag(zm_batch_s* b) {
     unsigned flag = 0;
-    ZM_HIP(hipMemcpy(&flag, b->d_zero + 1 + b->ngroups, sizeof(unsigned), hipMemcpyDeviceToHost));
+    ZM_HIP(hipMemcpy(&flag, b->d_zero + kCtrGroups + b->ngroups, sizeof(unsigned), hipMemcpyDeviceToHost));
     if (flag) return fail(ZM_EDEVICE, "batch kernel: a projection item waited past its bound");
     return ZM_OK;
 }
@@ -466,7 +615,7 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         foff[g] = fbytes;
         fbytes += align256((size_t)members[g].size() * (size_t)(p->n_max + 1) * 2 * p->Rp * sizeof(float));
     }
-    b->n_zero = 1 + b->ngroups + 1 + njobs;  // head, group counters, error flag, F16 max per frame
+    b->n_zero = kCtrGroups + b->ngroups + 1 + njobs;  // heads, group counters, error flag, F16 max per frame
     size_t n_items_max = 0;
     for (int i = 0; i < njobs; ++i) n_items_max += (size_t)b->plans[i]->Rp / (2 * pairs_of(b->plans[i]->A));
     for (int g = 0; g < b->ngroups; ++g) {
@@ -520,11 +669,11 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         j.fa.tw = (const float*)p->d_tw;
         j.fa.F = (float*)(b->d_mem + foff[g]) + (size_t)k * (p->n_max + 1) * 2 * p->Rp;
         // F16 max slots: contiguous per group, after head, counters and flag
-        j.fa.fmaxbuf = p->dtype == ZM_F16X2 ? (float*)(b->d_zero + 2 + b->ngroups + zoff[g] + k) : nullptr;
+        j.fa.fmaxbuf = p->dtype == ZM_F16X2 ? (float*)(b->d_zero + kCtrGroups + 1 + b->ngroups + zoff[g] + k) : nullptr;
         j.variant = a_index(p->A) * 5 + a2_index(p->A2);
         j.group = g;
         const int tiles = p->Rp / (2 * pairs_of(p->A));
-        for (int t = 0; t < tiles; ++t) b->stage1.push_back(BatchItem{0, i, t, 0});
+        for (int t = 0; t < tiles; ++t) b->stage1.push_back(BatchItem{0, i, t, g});
     }
     b->hgroups.resize(b->ngroups);
     for (int g = 0; g < b->ngroups; ++g) {
@@ -538,7 +687,7 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         G.pa.tlo = p->d_tlo;
         G.pa.rowscale = p->d_rowscale;
         G.pa.F = b->d_mem + foff[g];
-        G.pa.fmaxbuf = p->dtype == ZM_F16X2 ? (const float*)(b->d_zero + 2 + b->ngroups + zoff[g]) : nullptr;
+        G.pa.fmaxbuf = p->dtype == ZM_F16X2 ? (const float*)(b->d_zero + kCtrGroups + 1 + b->ngroups + zoff[g]) : nullptr;
         G.pa.B = n;
         G.pa.M = p->n_max + 1;
         G.pa.Rp = p->Rp;
@@ -548,7 +697,7 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         G.dtype = (int)p->dtype;
         G.tiles_total = (unsigned)(n * (p->Rp / (2 * pairs_of(p->A))));
         const int blocks = (G.pa.n_units + 7) / 8;
-        for (int k = 0; k < blocks; ++k) b->stage2.push_back(BatchItem{1, g, k, 0});
+        for (int k = 0; k < blocks; ++k) b->stage2.push_back(BatchItem{1, g, k, -1});
     }
     zm_status st = fill_pointers(b, jobs);
     if (st != ZM_OK) {

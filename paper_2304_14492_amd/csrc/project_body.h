@@ -44,7 +44,10 @@ struct ProjArgs {
 
 template <typename T>
 __device__ __forceinline__ T* zbase(const ProjArgs& a, int fr) {
-    return a.Z ? (T*)a.Z + (size_t)fr * a.Mtot * 2 : (T*)a.Zptrs[fr];
+    // the per-frame pointers are read as pointers to global memory, so that
+    // the stores through them are global stores rather than flat ones
+    using GP = __attribute__((address_space(1))) T*;
+    return a.Z ? (T*)a.Z + (size_t)fr * a.Mtot * 2 : (T*)((const GP*)(const void*)a.Zptrs)[fr];
 }
 
 // One wave: output block `unit` = (item unit / ncb, column block unit % ncb).
