@@ -134,8 +134,20 @@ __shared__ __attribute__((aligned(16))) char g_batch_smem[kBatchLds];
 // kernel); the kernel's occupancy target (4 waves per SIMD, two 512-thread
 // workgroups per CU, what the LDS allows anyway) bounds every body's
 // registers.
+// Claim of the next item of a range, issued before a tile body and read
+// after it, so that the atomic's latency hides behind the body (a barrier
+// waits for LDS operations only, not for this load).
+struct Claim {
+    unsigned* head;
+    int off, len;
+};
+
+// Runs one stage-1 tile; thread 0 claims the next item of `c`'s range on the
+// way and returns it (-1 on other threads or when the range is exhausted).
 template <int AI, int A2I>
-__device__ __attribute__((noinline)) void run_tile(const BatchJob* j, int tile) {
+__device__ __attribute__((noinline)) int run_tile(const BatchJob* j, int tile, Claim c) {
+    unsigned k = 0xffffffffu;
+    if (threadIdx.x == 0) k = atomicAdd(c.head, 1u);
     if constexpr (batch_variant_ok<kAList[AI], kA2List[A2I]>()) {
         FftArgs<float> fa = uniform_load(&j->fa);
         fa.src = global_field(&j->fa.src);
@@ -147,17 +159,18 @@ __device__ __attribute__((noinline)) void run_tile(const BatchJob* j, int tile) 
         tile = __builtin_amdgcn_readfirstlane(tile);
         polar_fft_tile<float, kAList[AI], kA2List[A2I], 512, kItemPairs>(fa, 0, tile, g_batch_smem);
     }
+    return k < (unsigned)c.len ? c.off + (int)k : -1;
 }
 
 template <int AI>
-__device__ __forceinline__ void run_tile_a2(const BatchJob* j, int a2i, int tile) {
+__device__ __forceinline__ int run_tile_a2(const BatchJob* j, int a2i, int tile, Claim c) {
     switch (a2i) {
-        case 0: run_tile<AI, 0>(j, tile); break;
-        case 1: run_tile<AI, 1>(j, tile); break;
-        case 2: run_tile<AI, 2>(j, tile); break;
-        case 3: run_tile<AI, 3>(j, tile); break;
-        case 4: run_tile<AI, 4>(j, tile); break;
-        default: break;
+        case 0: return run_tile<AI, 0>(j, tile, c);
+        case 1: return run_tile<AI, 1>(j, tile, c);
+        case 2: return run_tile<AI, 2>(j, tile, c);
+        case 3: return run_tile<AI, 3>(j, tile, c);
+        case 4: return run_tile<AI, 4>(j, tile, c);
+        default: return -1;
     }
 }
 
@@ -189,19 +202,26 @@ struct QueueInfo {
     int off[kQueues + 1];  // first item of each stage-1 range, then of stage 2
     int len[kQueues + 1];
 };
-// ctr[q] = head of range q (q <= kQueues), ctr[kQueues + 1 + g] = finished
-// tiles of group g, ctr[kQueues + 1 + n_groups] = error flag (a wait that hit
-// its bound)
-constexpr int kCtrGroups = kQueues + 1;
+// ctr[q] = head of range q (q <= kQueues), ctr[kQueues + 1] = released
+// stage-1 tiles of all groups, ctr[kCtrGroups + g] = released tiles of group
+// g, ctr[kCtrGroups + n_groups] = error flag (a wait that hit its bound)
+constexpr int kCtrTotal = kQueues + 1;
+constexpr int kCtrGroups = kQueues + 2;
 
 // Next item for a workgroup whose home range is `home` (thread 0 only): its
-// own range first, then the other stage-1 ranges, then stage 2.  Heads only
-// grow, so stage-2 items are taken only after every stage-1 item has been
-// taken, and a workgroup waiting in stage 2 holds no stage-1 item.
-__device__ __forceinline__ int pop_item(const QueueInfo& q, unsigned* ctr, int home) {
+// own range first (unless `skip_home`: a claim on it already failed), then
+// the other stage-1 ranges, then stage 2.  Heads only grow, so stage-2 items
+// are taken only after every stage-1 item has been taken, and a workgroup
+// waiting in stage 2 holds no stage-1 item.
+__device__ __forceinline__ int pop_item(const QueueInfo& q, unsigned* ctr, int home, bool skip_home) {
+    unsigned h[kQueues];  // all heads read at once: one round trip, not eight
+#pragma unroll
+    for (int d = 0; d < kQueues; ++d)
+        h[d] = __hip_atomic_load(&ctr[(home + d) % kQueues], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
     for (int d = 0; d < kQueues; ++d) {
         const int r = (home + d) % kQueues;
-        if (__hip_atomic_load(&ctr[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < (unsigned)q.len[r]) {
+        if ((d > 0 || !skip_home) && h[d] < (unsigned)q.len[r]) {
             const unsigned k = atomicAdd(&ctr[r], 1u);
             if (k < (unsigned)q.len[r]) return q.off[r] + (int)k;
         }
@@ -218,66 +238,74 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
     const int tid = threadIdx.x;
     // workgroups are dealt round-robin to the XCDs
     const int home = (int)(blockIdx.x % kQueues);
-    // Thread 0 takes the next item one ahead, so the atomics' latency
-    // overlaps the current item.  It also holds the workgroup's finished
-    // tiles that are not yet released (`pend` tiles of group `pend_group`).
-    // A release writes the XCD's L2 back, which stalls the gathers of every
-    // workgroup on that XCD, so it is done once per run of tiles of one
-    // group: when the next item is of another group, a stage-2 item (which
-    // may wait) or none.  No stage-2 item is popped while stage-1 items
-    // remain, and a workgroup releases before it takes one, so every wait
-    // still ends.
-    int next = 0, next_group = -1, pend_group = -1;
+    // Thread 0 holds the next item (claimed during the current one) and the
+    // workgroup's finished tiles that are not yet released (`pend` tiles of
+    // group `pend_group`).  A release writes the XCD's L2 back, which stalls
+    // the gathers of every workgroup on that XCD, so it is done once per run
+    // of tiles of one group: before a tile of another group, before a
+    // stage-2 item (which may wait) and before the exit.  No stage-2 item is
+    // popped while stage-1 items remain, and a workgroup releases before it
+    // runs one, so every wait still ends.
+    int next = 0, pend_group = -1;
     unsigned pend = 0;
-    if (tid == 0) {
-        next = pop_item(q, ctr, home);
-        if (next >= 0) next_group = items[next].group;
-    }
+    // Thread 0 also remembers what its last acquire covered: the group it
+    // waited for, or every group when all stage-1 tiles had been released
+    // by then.  An acquire invalidates the XCD's L2 (the radial tables that
+    // other projection items are reusing included), so it is done only when
+    // a stage-2 item's group is not covered yet.
+    int acq_group = -1;
+    bool acq_all = false;
+    // device-scope release of the workgroup's finished tiles (thread 0, after
+    // a barrier that every wave reached with its stores completed): writes
+    // the L2's dirty lines back; a release fence does not invalidate, so the
+    // XCD keeps the frame lines that other workgroups gather from
+    auto release = [&]() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomicAdd(&ctr[kCtrGroups + pend_group], pend);
+        atomicAdd(&ctr[kCtrTotal], pend);
+        pend = 0;
+    };
+    const Claim claim{&ctr[home], q.off[home], q.len[home]};
+    if (tid == 0) next = pop_item(q, ctr, home, false);
     for (;;) {
-        // previous item's LDS users are done and all its waves' stores have
-        // completed (each waited for them); `cur` is free
-        __syncthreads();
-        if (tid == 0) {
-            if (pend && next_group != pend_group) {
-                // device-scope release of the workgroup's tiles: writes the
-                // L2's dirty lines back (a release fence does not invalidate,
-                // so the XCD keeps the frame lines other workgroups gather)
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                atomicAdd(&ctr[kCtrGroups + pend_group], pend);
-                pend = 0;
-            }
-            cur = next;
-            if (next >= 0) {
-                next = pop_item(q, ctr, home);
-                next_group = next >= 0 ? items[next].group : -1;
-            }
-        }
+        __syncthreads();  // previous item's LDS users are done; `cur` is free
+        if (tid == 0) cur = next;
         __syncthreads();
         const int i = __builtin_amdgcn_readfirstlane(cur);  // uniform: scalar loads of the item and its job
-        if (i < 0) return;
+        if (i < 0) {
+            if (tid == 0 && pend) release();
+            return;
+        }
         const BatchItem it = items[i];
         if (it.kind == 0) {
+            if (tid == 0 && pend && it.group != pend_group) release();
             const BatchJob* j = jobs + it.idx;
             const int variant = j->variant;
             const int ai = variant / 5, a2i = variant % 5;
+            int claimed = -1;
             switch (ai) {
-                case 0: run_tile_a2<0>(j, a2i, it.sub); break;
-                case 1: run_tile_a2<1>(j, a2i, it.sub); break;
-                case 2: run_tile_a2<2>(j, a2i, it.sub); break;
-                case 3: run_tile_a2<3>(j, a2i, it.sub); break;
+                case 0: claimed = run_tile_a2<0>(j, a2i, it.sub, claim); break;
+                case 1: claimed = run_tile_a2<1>(j, a2i, it.sub, claim); break;
+                case 2: claimed = run_tile_a2<2>(j, a2i, it.sub, claim); break;
+                case 3: claimed = run_tile_a2<3>(j, a2i, it.sub, claim); break;
                 default: break;
             }
-            // this wave's spectra stores have reached the L2 before the
-            // barrier that precedes thread 0's release
+            // this wave's spectra stores have completed before the barriers
+            // that precede thread 0's release
             __builtin_amdgcn_s_waitcnt(0);
             if (tid == 0) {
                 pend_group = it.group;
                 ++pend;
+                next = claimed >= 0 ? claimed : pop_item(q, ctr, home, true);
             }
         } else {
             const BatchGroup* g = groups + it.idx;
             const unsigned need = g->tiles_total;
             if (tid == 0) {
+                if (pend) release();
+                next = pop_item(q, ctr, home, true);
+            }
+            if (tid == 0 && !acq_all && it.idx != acq_group) {
                 unsigned spins = 0;
                 while (__hip_atomic_load(&ctr[kCtrGroups + it.idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
                        need) {
@@ -287,9 +315,13 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
                         break;
                     }
                 }
-                // Acquire the group's spectra: invalidates this CU's vector
-                // cache and the XCD's L2, which every wave of the workgroup
-                // reads through; the barrier below orders their loads after it.
+                // Acquire the group's spectra (and, when every tile has been
+                // released, all groups'): invalidates this CU's vector cache
+                // and the XCD's L2, which every wave of the workgroup reads
+                // through; the barrier below orders their loads after it.
+                acq_all = __hip_atomic_load(&ctr[kCtrTotal], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >=
+                          (unsigned)q.off[kQueues];
+                acq_group = it.idx;
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             }
             __syncthreads();
