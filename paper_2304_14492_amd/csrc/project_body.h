@@ -79,9 +79,12 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
         const int frc = fr[u] < B ? fr[u] : B - 1;  // clamp: loads stay in bounds, results discarded
         boff[u] = ((size_t)frc * nRT * M + m) * 2 * zm::kRingTile + (size_t)(col[u] & 1) * zm::kRingTile;
     }
+    // operand rows of the two 16-row sub-tiles (zm::op_index layout): lane li's
+    // ring group at ring k starts at aoff[s] + k * 16
+    constexpr int kG = (DT == ZM_F64 || DT == ZM_F32) ? 4 : 8;
     size_t aoff[2];
 #pragma unroll
-    for (int s = 0; s < 2; ++s) aoff[s] = (size_t)(it.toff + it.row0 + 16 * s + li) * Rp;
+    for (int s = 0; s < 2; ++s) aoff[s] = zm::op_index(it.toff + it.row0 + 16 * s, 0, Rp, kG) + (size_t)li * kG;
 
     if constexpr (DT == ZM_F64) {
         const double* T = (const double*)thi;
@@ -93,8 +96,8 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (s == 1 && !two) break;
-                const double2 x0 = *(const double2*)(T + aoff[s] + kk);
-                const double2 x1 = *(const double2*)(T + aoff[s] + kk + 2);
+                const double2 x0 = *(const double2*)(T + aoff[s] + (size_t)kk * 16);
+                const double2 x1 = *(const double2*)(T + aoff[s] + (size_t)kk * 16 + 2);
                 a[s][0] = x0.x; a[s][1] = x0.y; a[s][2] = x1.x; a[s][3] = x1.y;
             }
 #pragma unroll
@@ -133,8 +136,8 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
         float4 a1[2], b1[2], a2[2], b2[2];
         auto load = [&](int k0, float4* a, float4* b) {
             const int kk = k0 + 4 * lg;
-            a[0] = *(const float4*)(T + aoff[0] + kk);
-            a[1] = two ? *(const float4*)(T + aoff[1] + kk) : float4{0.f, 0.f, 0.f, 0.f};
+            a[0] = *(const float4*)(T + aoff[0] + (size_t)kk * 16);
+            a[1] = two ? *(const float4*)(T + aoff[1] + (size_t)kk * 16) : float4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int u = 0; u < 2; ++u) b[u] = *(const float4*)(F + boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg);
         };
@@ -191,11 +194,11 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
         float4 ny[2][2];
         auto load = [&](int k0) {
             const int kk = k0 + 8 * lg;
-            nah[0] = *(const H8*)(Th + aoff[0] + kk);
-            nal[0] = *(const H8*)(Tl + aoff[0] + kk);
+            nah[0] = *(const H8*)(Th + aoff[0] + (size_t)kk * 16);
+            nal[0] = *(const H8*)(Tl + aoff[0] + (size_t)kk * 16);
             if (two) {
-                nah[1] = *(const H8*)(Th + aoff[1] + kk);
-                nal[1] = *(const H8*)(Tl + aoff[1] + kk);
+                nah[1] = *(const H8*)(Th + aoff[1] + (size_t)kk * 16);
+                nal[1] = *(const H8*)(Tl + aoff[1] + (size_t)kk * 16);
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {

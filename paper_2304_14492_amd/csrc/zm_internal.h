@@ -55,6 +55,17 @@ constexpr int kRingTile = 16;   // rings per resample+FFT workgroup
 constexpr int kRingPad = 32;    // rings padded to a multiple of this (projection K step)
 constexpr int kRowTile = 16;    // projection rows per MFMA tile (per m block)
 
+// Position of entry (row, ring r) in the projection operand table.  Rows come
+// in blocks of kRowTile (one MFMA row tile); inside a block the rings come in
+// groups of g (the consecutive rings one lane reads for one MFMA fragment: 4
+// for FP32/FP64, 8 for the 16-bit splits), and a group holds its g rings for
+// each of the block's 16 rows in turn.  So the 16 lanes that read one
+// fragment read 16 * g contiguous entries, and each group of 4 lanes one
+// 64-byte run (the texture path coalesces within groups of 4 lanes).
+__host__ __device__ inline size_t op_index(int row, int r, int Rp, int g) {
+    return ((size_t)(row / kRowTile) * Rp + (size_t)(r / g) * g) * kRowTile + (size_t)(row % kRowTile) * g + r % g;
+}
+
 // Canonical position of (n, m) (n ascending, then m ascending, m = n mod 2 .. n step 2).
 __host__ __device__ inline int canon_index(int n, int m) {
     int p = n >> 1;
