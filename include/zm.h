@@ -140,8 +140,10 @@ zm_status zm_moments(zm_plan_t plan, const void* d_images, int batch, long long 
 /* The two stages of zm_moments, for callers that want the ring spectra or
  * time the stages separately.  zm_spectra runs the fused resample + angular
  * FFT and leaves F_r[m] = sum_a f^(rho_r, theta_a) exp(-2 pi i m a / A) for
- * m = 0..n_max in the workspace (layout [batch][m][re|im][rings_padded],
- * FP32, or FP64 for ZM_F64); zm_project applies the radial projection to the
+ * m = 0..n_max in the workspace (FP32, or FP64 for ZM_F64), blocked by 16
+ * rings: element (frame b, ring r, m, part c: 0 = re, 1 = im) sits at
+ * [b][r / 16][m][c][r % 16] over rings_padded rings; zm_project applies the
+ * radial projection to the
  * spectra of a preceding zm_spectra call on the same workspace and stream.
  * zm_moments == zm_spectra followed by zm_project. */
 zm_status zm_spectra(zm_plan_t plan, const void* d_images, int batch, long long image_stride, void* d_ws,

@@ -99,6 +99,31 @@ def test_config4_batch_graph_autotune(zm):
     b.close()
 
 
+@pytest.mark.parametrize("specs", [
+    [(192, 20, 11)],                    # one small frame: fewer tiles than the 8 queue ranges
+    [(192, 20, 12), (320, 40, 13)],     # two plans, a few tiles each
+])
+def test_batch_fewer_tiles_than_ranges(zm, specs):
+    # Most stage-1 ranges are empty: workgroups take tiles from other ranges
+    # or go straight to the projection items, whose wait must still end with
+    # every group's tiles released; replays reset the queue counters.
+    frames = _frames(specs)
+    plans = _plans(zm, specs)
+    b = zm.Batch(plans, frames, graph=True)
+    assert b.config()["n_items"] < 64
+    ref = [p.moments(f) for p, f in zip(plans, frames)]
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for z in b.outs:
+            z.fill_(float("nan"))
+        b.run()
+        torch.cuda.synchronize()
+        for z, r in zip(b.outs, ref):
+            assert torch.equal(z, r), rep
+    b.check()
+    b.close()
+
+
 def test_batch_rejects_unsupported(zm):
     f = torch.zeros(64, 64, device="cuda", dtype=torch.float64)
     p = zm.Plan(10, 64, 64, dtype="f64")
