@@ -223,9 +223,12 @@ zm_status zm_recon_workspace_size(zm_plan_t plan, int batch, size_t* bytes);
 
 /* Reconstruction error over the disk (pixel centres with rho <= 1) between
  * frames d_ref and reconstructions d_recon ([batch][H][W]).  host_out
- * receives batch rows of 5 doubles: eq. (13) epsilon = SSE / (f_max^2 * count),
- * eq. (10) epsilon_1 = SSE / sum f^2, SSE, f_max = max |f|, count.
- * Deterministic (fixed reduction order).  Synchronises the stream. */
+ * receives batch rows of 7 doubles: eq. (13) epsilon = SSE / (f_max^2 * count),
+ * eq. (10) epsilon_1 = SSE / sum f^2, SSE, f_max = max |f|, count,
+ * eq. (12) epsilon_2 = sum (f - f~)^2 / f^2 over the disk pixels with f != 0
+ * (the measure is singular where f = 0), and the number of disk pixels with
+ * f = 0 that it leaves out.  Deterministic (fixed reduction order).
+ * Synchronises the stream. */
 zm_status zm_recon_error(zm_plan_t plan, const void* d_ref, const void* d_recon, int batch, double* host_out,
                          void* d_ws, size_t ws_bytes, zm_stream_t stream);
 

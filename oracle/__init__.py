@@ -293,15 +293,20 @@ def reconstruct_polar(Z: np.ndarray, nmax: int, R: int, A: int, neumann: bool = 
 
 def recon_error(f: np.ndarray, ft: np.ndarray, mask: np.ndarray) -> dict:
     """Eq. (13): sum_disk (f - f~)^2 / (f_max^2 * count_disk); also sqrt (NRMSE)
-    and -10 log10 (a PSNR in dB); eq. (10) for context."""
+    and -10 log10 (a PSNR in dB); eq. (10) for context; eq. (12):
+    sum_disk (f - f~)^2 / f^2 over the pixels with f != 0 (the measure is
+    singular where f = 0; ``zeros`` counts the disk pixels it leaves out)."""
     fd = f[mask].astype(np.float64)
     td = ft[mask].astype(np.float64)
     fmax = float(np.max(np.abs(fd))) if fd.size else 0.0
     sse = float(np.sum((fd - td) ** 2))
     eps = sse / (fmax * fmax * fd.size) if fmax > 0 else float("nan")
     e1 = sse / float(np.sum(fd * fd)) if np.any(fd) else float("nan")
+    nz = fd != 0.0
+    e2 = float(np.sum((fd[nz] - td[nz]) ** 2 / (fd[nz] * fd[nz])))
     return dict(eps13=eps, nrmse=math.sqrt(eps) if eps == eps else eps,
-                psnr_db=-10.0 * math.log10(eps) if eps and eps > 0 else float("inf"), eps10=e1)
+                psnr_db=-10.0 * math.log10(eps) if eps and eps > 0 else float("inf"), eps10=e1,
+                eps12=e2, zeros=int(np.count_nonzero(~nz)))
 
 
 def minmax(ft: np.ndarray, f: np.ndarray, mask: np.ndarray) -> np.ndarray:

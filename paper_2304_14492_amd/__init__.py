@@ -309,18 +309,20 @@ def reconstruct(plan, Z, kind="cartesian", one_sided=False, minmax_ref=None, str
 
 
 def recon_error(plan, ref, recon, stream=None):
-    """eq. (13) (and eq. (10)) per frame over the disk: list of dicts."""
+    """eq. (13), eq. (10) and eq. (12) per frame over the disk: list of dicts
+    (eps12 covers the pixels with f != 0; zeros counts those left out)."""
     import numpy as np
     if ref.dim() == 2:
         ref, recon = ref.unsqueeze(0), recon.unsqueeze(0)
     ref, recon = ref.contiguous(), recon.contiguous()
     B = ref.shape[0]
     ws = _recon_ws(plan, B, ref.device)
-    out = np.empty((B, 5), dtype=np.float64)
+    out = np.empty((B, 7), dtype=np.float64)
     _check(_lib.zm_recon_error(plan._h, _vp(ref.data_ptr()), _vp(recon.data_ptr()), B,
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _vp(ws.data_ptr()), ws.numel(),
                                _stream_handle(stream)), "zm_recon_error")
-    return [dict(eps13=r[0], eps10=r[1], sse=r[2], fmax=r[3], count=int(r[4])) for r in out]
+    return [dict(eps13=r[0], eps10=r[1], sse=r[2], fmax=r[3], count=int(r[4]), eps12=r[5], zeros=int(r[6]))
+            for r in out]
 
 
 BATCH_AUTOTUNE, BATCH_NO_GRAPH = 1, 2

@@ -490,7 +490,8 @@ zm_status zm_recon_workspace_size(zm_plan_t p, int batch, size_t* bytes) {
     if (!p || !bytes) return fail(ZM_EINVAL, "null plan or output");
     if (batch < 0) return fail(ZM_EINVAL, "negative batch");
     const size_t nblk = recon_reduce_blocks(p);
-    *bytes = align256((size_t)batch * nblk * 4 * sizeof(double)) + align256((size_t)batch * 5 * sizeof(double));
+    *bytes = align256((size_t)batch * nblk * kErrParts * sizeof(double)) +
+             align256((size_t)batch * kErrOut * sizeof(double));
     return ZM_OK;
 }
 
@@ -537,10 +538,11 @@ zm_status zm_recon_error(zm_plan_t p, const void* d_ref, const void* d_recon, in
     ZM_DEVICE(p->device);
     hipStream_t s = (hipStream_t)stream;
     double* part = (double*)d_ws;
-    double* out = (double*)((char*)d_ws + align256((size_t)batch * recon_reduce_blocks(p) * 4 * sizeof(double)));
+    double* out =
+        (double*)((char*)d_ws + align256((size_t)batch * recon_reduce_blocks(p) * kErrParts * sizeof(double)));
     hipError_t e = launch_recon_error(p, d_ref, d_recon, batch, part, out, s);
     if (e != hipSuccess) return hip_fail(e, "error kernel launch");
-    ZM_HIP(hipMemcpyAsync(host_out, out, (size_t)batch * 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+    ZM_HIP(hipMemcpyAsync(host_out, out, (size_t)batch * kErrOut * sizeof(double), hipMemcpyDeviceToHost, s));
     ZM_HIP(hipStreamSynchronize(s));
     return ZM_OK;
 }

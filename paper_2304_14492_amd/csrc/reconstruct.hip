@@ -139,52 +139,63 @@ __global__ __launch_bounds__(kThreads) void error_partial_kernel(const FT* __res
                                                                  int H, int W, double* __restrict__ part) {
     const int b = blockIdx.y;
     const long p = (long)blockIdx.x * kThreads + threadIdx.x;
-    __shared__ double s0[kThreads], s1[kThreads], s2[kThreads], s3[kThreads];
-    double sse = 0.0, sf2 = 0.0, fm = 0.0, cnt = 0.0;
+    __shared__ double sh[zm::kErrParts][kThreads];
+    // per pixel of the disk: (f - f~)^2, f^2, |f|, 1, (f - f~)^2 / f^2 where
+    // f != 0 (eq. (12) is singular where f = 0), and 1 where f = 0
+    double v[zm::kErrParts] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     if (p < (long)H * W) {
         const int i = (int)(p / W), jx = (int)(p % W);
         const int D = min(H, W);
         const long X = 2L * jx - (W - 1), Y = (long)(H - 1) - 2L * i;
         if (X * X + Y * Y <= (long)D * D) {
             const double fv = (double)f[(size_t)b * H * W + p], gv = (double)g[(size_t)b * H * W + p];
-            sse = (fv - gv) * (fv - gv);
-            sf2 = fv * fv;
-            fm = fabs(fv);
-            cnt = 1.0;
+            const double d2 = (fv - gv) * (fv - gv);
+            v[0] = d2;
+            v[1] = fv * fv;
+            v[2] = fabs(fv);
+            v[3] = 1.0;
+            if (fv != 0.0)
+                v[4] = d2 / (fv * fv);
+            else
+                v[5] = 1.0;
         }
     }
     const int t = threadIdx.x;
-    s0[t] = sse; s1[t] = sf2; s2[t] = fm; s3[t] = cnt;
+#pragma unroll
+    for (int k = 0; k < zm::kErrParts; ++k) sh[k][t] = v[k];
     __syncthreads();
     for (int s = kThreads / 2; s > 0; s >>= 1) {
         if (t < s) {
-            s0[t] += s0[t + s];
-            s1[t] += s1[t + s];
-            s2[t] = fmax(s2[t], s2[t + s]);
-            s3[t] += s3[t + s];
+#pragma unroll
+            for (int k = 0; k < zm::kErrParts; ++k)
+                sh[k][t] = k == 2 ? fmax(sh[k][t], sh[k][t + s]) : sh[k][t] + sh[k][t + s];
         }
         __syncthreads();
     }
     if (t == 0) {
-        double* o = part + ((size_t)b * gridDim.x + blockIdx.x) * 4;
-        o[0] = s0[0]; o[1] = s1[0]; o[2] = s2[0]; o[3] = s3[0];
+        double* o = part + ((size_t)b * gridDim.x + blockIdx.x) * zm::kErrParts;
+#pragma unroll
+        for (int k = 0; k < zm::kErrParts; ++k) o[k] = sh[k][0];
     }
 }
 
 __global__ void error_final_kernel(const double* __restrict__ part, int nblk, double* __restrict__ out) {
     const int b = blockIdx.x;
     if (threadIdx.x != 0) return;
-    double sse = 0.0, sf2 = 0.0, fm = 0.0, cnt = 0.0;
+    double q[zm::kErrParts] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < nblk; ++k) {
-        const double* q = part + ((size_t)b * nblk + k) * 4;
-        sse += q[0]; sf2 += q[1]; fm = fmax(fm, q[2]); cnt += q[3];
+        const double* r = part + ((size_t)b * nblk + k) * zm::kErrParts;
+        for (int c = 0; c < zm::kErrParts; ++c) q[c] = c == 2 ? fmax(q[c], r[c]) : q[c] + r[c];
     }
-    double* o = out + (size_t)b * 5;
+    const double sse = q[0], sf2 = q[1], fm = q[2], cnt = q[3];
+    double* o = out + (size_t)b * zm::kErrOut;
     o[0] = (fm > 0.0 && cnt > 0.0) ? sse / (fm * fm * cnt) : 0.0;  // eq. (13)
     o[1] = sf2 > 0.0 ? sse / sf2 : 0.0;                             // eq. (10)
     o[2] = sse;
     o[3] = fm;
     o[4] = cnt;
+    o[5] = q[4];  // eq. (12) over the pixels with f != 0
+    o[6] = q[5];  // pixels of the disk with f = 0 (left out of eq. (12))
 }
 
 // min / max over the disk of the reference (band) and of the reconstruction.

@@ -54,6 +54,8 @@ constexpr int kMaxRings = 4096;
 constexpr int kRingTile = 16;   // rings per resample+FFT workgroup
 constexpr int kRingPad = 32;    // rings padded to a multiple of this (projection K step)
 constexpr int kRowTile = 16;    // projection rows per MFMA tile (per m block)
+constexpr int kErrParts = 6;    // partial sums per block of the reconstruction-error reduction
+constexpr int kErrOut = 7;      // doubles per frame returned by zm_recon_error
 
 // Position of entry (row, ring r) in the projection operand table.  Rows come
 // in blocks of kRowTile (one MFMA row tile); inside a block the rings come in

@@ -97,11 +97,29 @@ def test_round_trip_error_and_minmax(zm):
     assert abs(err["eps13"] - ref["eps13"]) <= 1e-6 * ref["eps13"] + 1e-12
     assert abs(err["eps10"] - ref["eps10"]) <= 1e-6 * ref["eps10"] + 1e-12
     assert err["count"] == int(mask.sum())
+    assert abs(err["eps12"] - ref["eps12"]) <= 1e-6 * ref["eps12"] + 1e-12
+    assert err["zeros"] == ref["zeros"]
     assert err["eps13"] < 0.01  # smooth content is well captured at order 40
     mm = zm.reconstruct(plan, Z, kind="cartesian", minmax_ref=ft).cpu().numpy()[0]
     mmo = oracle.minmax(reco, f.astype(np.float64), mask)
     assert np.max(np.abs(mm - mmo)) <= 1e-5 * np.max(np.abs(mmo))
     assert abs(mm[mask].min() - f[mask].min()) < 1e-5 and abs(mm[mask].max() - f[mask].max()) < 1e-5
+
+
+def test_error_measures_with_zero_pixels(zm):
+    # eq. (12) leaves out the disk pixels where f = 0; eq. (10)/(13) keep them
+    H, W = 96, 80
+    plan = zm.Plan(10, H, W, dtype="f32")
+    rng = np.random.default_rng(21)
+    f = rng.uniform(0.5, 2.0, size=(H, W)).astype(np.float32)
+    f[30:50, 20:45] = 0.0                       # a zero block inside the disk
+    g = (f + rng.normal(0.0, 0.05, size=(H, W))).astype(np.float32)
+    err = zm.recon_error(plan, torch.from_numpy(f).cuda(), torch.from_numpy(g).cuda())[0]
+    mask, *_ = oracle.disk_pixels(H, W)
+    ref = oracle.recon_error(f.astype(np.float64), g.astype(np.float64), mask)
+    assert ref["zeros"] == 500 and err["zeros"] == ref["zeros"]
+    for k in ("eps12", "eps13", "eps10"):
+        assert abs(err[k] - ref[k]) <= 1e-12 * abs(ref[k]), k
 
 
 def test_neumann_moments_reconstruct_same_image(zm):

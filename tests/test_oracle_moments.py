@@ -201,3 +201,9 @@ def test_recon_error_eq13():
     # sum over disk of f^2 = 0 + 4 + 1 = 5; f_max = 2; count = 3
     assert abs(r["eps13"] - 5.0 / (4.0 * 3)) < 1e-15
     assert abs(r["eps10"] - 1.0) < 1e-15
+    # eq. (12) over the disk pixels with f != 0: (2 - 0)^2 / 4 + (1 - 0)^2 / 1 = 2;
+    # the disk pixel with f = 0 is left out (the one outside the disk never counts)
+    assert abs(r["eps12"] - 2.0) < 1e-15 and r["zeros"] == 1
+    r = oracle.recon_error(f, 0.5 * f, mask)
+    # every non-zero pixel is off by half of itself: 2 pixels x 1/4
+    assert abs(r["eps12"] - 0.5) < 1e-15 and r["zeros"] == 1
