@@ -46,6 +46,10 @@ NMAX, RINGS, ANGLES = 200, 1080, 4096
 DISTINCT = 4          # distinct seeded frames (seeds 3..6), tiled to fill the batch
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16x2": 2500.0, "f16x2": 2500.0}
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+# pixel-centre reconstruction, per (disk pixel, moment): the recurrence step
+# (alpha x + beta) q1 + gamma q2 (5 flops) and the complex accumulation (4)
+RECON_FLOPS_PER_PIXEL_MOMENT = 9
 METRIC = "4K images/s at N_max=200 (FP32 vs split-BF16) + p50/p99 latency at fixed QPS"
 
 
@@ -215,6 +219,35 @@ def batch_form(steps):
             "per_plan_launches_ms": round(ms_plan, 4)}
 
 
+def reconstruction(reps=3):
+    """eq. (9) reconstruction of one benchmark 4K frame from its N_max = 200
+    moments: at the pixel centres (FP64 recurrence per pixel) and at the
+    plan's polar nodes (FP64 table of eq. (7))."""
+    import torch
+    import paper_2304_14492_amd as zm
+    f = torch.from_numpy(make_frames(1)[0]).cuda()[None]
+    plan = zm.Plan(NMAX, H, W, dtype="f32", rings=RINGS, angles=ANGLES)
+    Z = plan.moments(f)
+    out = {"frame": [H, W], "n_max": NMAX}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for kind in ("cartesian", "polar"):
+        zm.reconstruct(plan, Z, kind=kind)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            zm.reconstruct(plan, Z, kind=kind)
+        e1.record()
+        torch.cuda.synchronize()
+        out[f"{kind}_ms"] = round(e0.elapsed_time(e1) / reps, 3)
+    n_disk = int(disk_pixels(H, W))
+    flops = RECON_FLOPS_PER_PIXEL_MOMENT * n_disk * plan.num_moments
+    tf = flops / (out["cartesian_ms"] / 1e3) / 1e12
+    out["cartesian_roofline"] = {"bound": "alu", "kernel": "recon_cart_kernel", "achieved": round(tf, 2),
+                                 "peak": FP64_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4), "flops": flops}
+    return out
+
+
 def serving(dtype, count, qps, warmup_s):
     """Serving form for one projection dtype: saturation throughput (every
     request queued at t = 0), then Poisson streams at the fixed rate `qps` and
@@ -264,6 +297,7 @@ def main():
     ap.add_argument("--requests", type=int, default=10000,
                     help="at most this many requests per serving run (0 skips serving)")
     ap.add_argument("--no-batch-form", action="store_true")
+    ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction timing")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters into bytes")
@@ -335,6 +369,10 @@ def main():
         torch.cuda.empty_cache()
         res["batch_form"] = batch_form(args.steps)
         print(f"[bench] batch form: {res['batch_form']}", file=sys.stderr, flush=True)
+    if not args.no_recon:
+        torch.cuda.empty_cache()
+        res["reconstruction"] = reconstruction()
+        print(f"[bench] reconstruction: {res['reconstruction']}", file=sys.stderr, flush=True)
     if args.requests > 0:
         torch.cuda.empty_cache()
         res["latency"] = {}

@@ -102,7 +102,7 @@ static void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w
 
 static void free_plan(zm_plan_s* p) {
     if (!p) return;
-    void* bufs[] = {p->d_spx, p->d_trig, p->d_tw, p->d_table, p->d_thi,
+    void* bufs[] = {p->d_spx, p->d_trig, p->d_tw, p->d_table, p->d_jac, p->d_thi,
                     p->d_tlo, p->d_rowscale, p->d_items, p->d_rowmap};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
@@ -296,6 +296,7 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
     ZM_TRY(dev_alloc(&p->d_spx, R, &total));
     ZM_TRY(dev_alloc(&p->d_trig, 2 * (size_t)A, &total));
     ZM_TRY(dev_alloc(&p->d_table, (size_t)p->num_moments * R, &total));
+    ZM_TRY(dev_alloc(&p->d_jac, 3 * (size_t)p->num_moments, &total));
     const bool with_moments = moments_supported(p);
     if (with_moments) {
         const size_t n = (size_t)p->table_rows * p->Rp;
@@ -332,6 +333,33 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
     ZM_TRYHIP(hipMemcpy(d_ck, ckc.data(), p->NK * sizeof(double), hipMemcpyHostToDevice));
     ZM_TRYHIP(hipMemcpy(p->d_spx, spx.data(), R * sizeof(double), hipMemcpyHostToDevice));
     ZM_TRYHIP(hipMemcpy(p->d_trig, trig.data(), 2 * (size_t)A * sizeof(double), hipMemcpyHostToDevice));
+    {
+        // Pixel-centre reconstruction: R_n^m(rho) = rho^m Q_k(x), x = 1 - 2 rho^2,
+        // k = (n - m) / 2, Q_k = (-1)^k P_k^(m,0)(x) (Jacobi), by the three-term
+        // recurrence Q_k = (alpha x + beta) Q_{k-1} + gamma Q_{k-2}, Q_0 = 1.
+        // The coefficients depend on (k, m) only: one (alpha, beta, gamma) per moment.
+        std::vector<double> jac(3 * (size_t)p->num_moments, 0.0);
+        for (int n = 0; n <= p->n_max; ++n)
+            for (int m = n & 1; m <= n; m += 2) {
+                const int k = (n - m) / 2;
+                const double kk = k, am = m;
+                double al = 0.0, be = 0.0, ga = 0.0;
+                if (k == 1) {
+                    al = 0.5 * (am + 2.0);
+                    be = 0.5 * am;
+                } else if (k >= 2) {
+                    const double a1 = 2.0 * kk * (kk + am) * (2.0 * kk + am - 2.0);
+                    al = (2.0 * kk + am - 1.0) * (2.0 * kk + am) * (2.0 * kk + am - 2.0) / a1;
+                    be = (2.0 * kk + am - 1.0) * am * am / a1;
+                    ga = 2.0 * (kk + am - 1.0) * (kk - 1.0) * (2.0 * kk + am) / a1;
+                }
+                double* j = &jac[3 * (size_t)canon_index(n, m)];
+                j[0] = -al;  // the (-1)^k of R_n^m folded into the recurrence
+                j[1] = -be;
+                j[2] = -ga;
+            }
+        ZM_TRYHIP(hipMemcpy(p->d_jac, jac.data(), jac.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     if (with_moments) {
         if (p->dtype == ZM_F64) {
             ZM_TRYHIP(hipMemcpy(p->d_tw, trig.data(), 2 * (size_t)A * sizeof(double), hipMemcpyHostToDevice));

@@ -71,10 +71,13 @@ __global__ __launch_bounds__(kThreads) void recon_polar_kernel(const ZT* __restr
 
 // One thread per pixel centre: rho^2 = P / D^2 with the integer
 // P = (2j - (W-1))^2 + ((H-1) - 2i)^2; pixels with rho > 1 are set to 0.
+// Per m, S_m = sum_k Z_{m+2k,m} Q_k(x) with the plan's recurrence
+// coefficients (jac: alpha, beta, gamma per moment; the same for every pixel,
+// read with scalar loads), then f~ += c_m rho^m Re(S_m exp(j m theta)).
 template <typename ZT, typename OT>
 __global__ __launch_bounds__(kThreads) void recon_cart_kernel(const ZT* __restrict__ Zall, int Mtot, int nmax, int H,
-                                                              int W, int neumann, int one_sided,
-                                                              OT* __restrict__ out) {
+                                                              int W, const double* __restrict__ jac, int neumann,
+                                                              int one_sided, OT* __restrict__ out) {
     const int b = blockIdx.y;
     const long p = (long)blockIdx.x * kThreads + threadIdx.x;
     if (p >= (long)H * W) return;
@@ -97,33 +100,20 @@ __global__ __launch_bounds__(kThreads) void recon_cart_kernel(const ZT* __restri
     double rm = 1.0;            // rho^m
     double acc = 0.0;
     for (int m = 0; m <= nmax; ++m) {
-        // S_m = sum_k Z_{m+2k, m} R_{m+2k}^m(rho)
-        double sr = 0.0, si = 0.0;
-        const double am = (double)m;
-        double pkm2 = 0.0, pkm1 = 1.0;  // P_{k-2}, P_{k-1}; P_0 = 1
-        for (int k = 0; m + 2 * k <= nmax; ++k) {
-            double pk;
-            if (k == 0) {
-                pk = 1.0;
-            } else if (k == 1) {
-                pk = 0.5 * ((am + 2.0) * x + am);
-            } else {
-                const double kk = (double)k;
-                const double a1 = 2.0 * kk * (kk + am) * (2.0 * kk + am - 2.0);
-                const double a2 = (2.0 * kk + am - 1.0) * ((2.0 * kk + am) * (2.0 * kk + am - 2.0) * x + am * am);
-                const double a3 = 2.0 * (kk + am - 1.0) * (kk - 1.0) * (2.0 * kk + am);
-                pk = (a2 * pkm1 - a3 * pkm2) / a1;
-            }
-            if (k >= 1) {
-                pkm2 = pkm1;
-                pkm1 = pk;
-            }
-            const double rv = ((k & 1) ? -1.0 : 1.0) * rm * pk;
-            const int idx = zm::canon_index(m + 2 * k, m);
-            sr += rv * zre(Z, idx);
-            si += rv * zim(Z, idx);
+        int idx = zm::canon_index(m, m);
+        double sr = zre(Z, idx), si = zim(Z, idx);  // Q_0 = 1
+        double q1 = 1.0, q2 = 0.0;                    // Q_{k-1}, Q_{k-2}
+#pragma unroll 4
+        for (int n = m + 2; n <= nmax; n += 2) {
+            idx = zm::canon_index(n, m);
+            const double* J = jac + 3 * (size_t)idx;
+            const double q = (J[0] * x + J[1]) * q1 + J[2] * q2;
+            q2 = q1;
+            q1 = q;
+            sr += q * zre(Z, idx);
+            si += q * zim(Z, idx);
         }
-        acc += coef_m(m, neumann, one_sided) * (sr * cm - si * sm);
+        acc += coef_m(m, neumann, one_sided) * rm * (sr * cm - si * sm);
         const double cn = cm * c1 - sm * s1, sn = sm * c1 + cm * s1;
         cm = cn;
         sm = sn;
@@ -315,10 +305,10 @@ hipError_t launch_recon_cart(const zm_plan_s* p, const void* Z, int batch, void*
     dim3 grid((unsigned)((npx + kThreads - 1) / kThreads), batch);
     if (p->dtype == ZM_F64)
         hipLaunchKernelGGL((recon_cart_kernel<double, double>), grid, dim3(kThreads), 0, s, (const double*)Z,
-                           p->num_moments, p->n_max, p->H, p->W, p->neumann, one_sided, (double*)out);
+                           p->num_moments, p->n_max, p->H, p->W, p->d_jac, p->neumann, one_sided, (double*)out);
     else
         hipLaunchKernelGGL((recon_cart_kernel<float, float>), grid, dim3(kThreads), 0, s, (const float*)Z,
-                           p->num_moments, p->n_max, p->H, p->W, p->neumann, one_sided, (float*)out);
+                           p->num_moments, p->n_max, p->H, p->W, p->d_jac, p->neumann, one_sided, (float*)out);
     return hipGetLastError();
 }
 

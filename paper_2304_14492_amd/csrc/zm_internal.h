@@ -106,6 +106,7 @@ struct zm_plan_s {
     double* d_trig = nullptr;            // cos/sin(2 pi a / A), [A][2]
     void* d_tw = nullptr;                // FFT twiddles exp(-2 pi i j / A) as (cos, sin), [A][2]
     double* d_table = nullptr;           // R_nm(rho_r), [num_moments][R], FP64 (eq. (7))
+    double* d_jac = nullptr;             // per moment (alpha, beta, gamma) of the pixel-centre recurrence
     void* d_thi = nullptr;               // projection operand (or its hi part)
     void* d_tlo = nullptr;               // lo part (split dtypes)
     float* d_rowscale = nullptr;         // per operand row: factor undoing the F16 row scaling
