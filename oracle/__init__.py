@@ -69,6 +69,8 @@ def _lib():
         L.zmo_radial_sum.restype = None
         L.zmo_cartesian.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
         L.zmo_cartesian.restype = ctypes.c_int
+        L.zmo_cartesian_one.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+        L.zmo_cartesian_one.restype = ctypes.c_int
         L.zmo_reconstruct.argtypes = [dp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, dp]
         L.zmo_reconstruct.restype = None
         _lib_handle = L
@@ -230,8 +232,22 @@ def moments(frame: np.ndarray, nmax: int, R: int, A: int, neumann: bool = False,
 
 
 # ---------------------------------------------------------------------------
-# Eq. (3) + (5): Cartesian pixel sum (sanity reference only).
+# Eq. (3) + (5) / eq. (6), (14): Cartesian pixel sum.
 # ---------------------------------------------------------------------------
+def cartesian_moment(frame: np.ndarray, n: int, m: int, neumann: bool = False) -> complex:
+    """One moment Z_nm of the Cartesian pixel sum (eq. (6); eq. (14) with
+    ``neumann``), R_nm exact (eq. (2), big-integer) at every disk pixel centre;
+    m < 0 through Z_{n,-m} = conj(Z_nm)."""
+    f = np.ascontiguousarray(frame, dtype=np.float64)
+    H, W = f.shape
+    Z = np.empty(2, dtype=np.float64)
+    rc = _lib().zmo_cartesian_one(_p(f, ctypes.c_double), H, W, int(n), int(m), int(bool(neumann)),
+                                  _p(Z, ctypes.c_double))
+    if rc != 0:
+        raise ValueError(f"bad moment (n, m) = ({n}, {m})")
+    return complex(Z[0], Z[1])
+
+
 def cartesian(frame: np.ndarray, nmax: int, neumann: bool = False) -> np.ndarray:
     f = np.ascontiguousarray(frame, dtype=np.float64)
     H, W = f.shape

@@ -484,6 +484,55 @@ int zmo_cartesian(const double* f, int H, int W, int nmax, int neumann, double* 
     return bad ? -1 : 0;
 }
 
+/* One moment of the same Cartesian sum, Z~_nm for a single (n, m) with
+ * |m| <= n and n - |m| even (m < 0 through Z_{n,-m} = conj(Z_nm), Sec. 2);
+ * eq. (14) divides by the Neumann factor eps_m when `neumann` is set.  Z
+ * receives (re, im).  Returns 0, or -1 for a bad (n, m). */
+int zmo_cartesian_one(const double* f, int H, int W, int n, int m, int neumann, double* Z) {
+    int am = m < 0 ? -m : m;
+    if (n < 0 || am > n || ((n - am) & 1)) return -1;
+    int D = H < W ? H : W;
+    long npx = 0;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            long X = 2L * j - (W - 1), Y = (H - 1) - 2L * i;
+            if (X * X + Y * Y <= (long)D * D) ++npx;
+        }
+    uint64_t* P = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(npx + 1));
+    uint64_t* ones = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)(npx + 1));
+    int* zeros = (int*)calloc((size_t)(npx + 1), sizeof(int));
+    double* rv = (double*)malloc(sizeof(double) * (size_t)(npx + 1));
+    long c = 0;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            long X = 2L * j - (W - 1), Y = (H - 1) - 2L * i;
+            if (X * X + Y * Y <= (long)D * D) {
+                P[c] = (uint64_t)(X * X + Y * Y);
+                ones[c] = 1;
+                ++c;
+            }
+        }
+    int rc = zmo_zrp_column(n, am, (uint64_t)D, (uint64_t)D, 0, (int)npx, P, ones, zeros, rv);
+    double re = 0.0, im = 0.0;
+    c = 0;
+    for (int i = 0; i < H; ++i)
+        for (int j = 0; j < W; ++j) {
+            long X = 2L * j - (W - 1), Y = (H - 1) - 2L * i;
+            if (X * X + Y * Y <= (long)D * D) {
+                double th = atan2((double)Y, (double)X);
+                double v = f[(size_t)i * W + j] * rv[c++];
+                re += v * cos(am * th);
+                im -= v * sin(am * th);
+            }
+        }
+    double eps = (neumann && am == 0) ? 2.0 : 1.0;
+    double k = (double)(n + 1) / (M_PI * eps) * (2.0 / D) * (2.0 / D);
+    Z[0] = k * re;
+    Z[1] = (m < 0 ? -k : k) * im;
+    free(P); free(ones); free(zeros); free(rv);
+    return rc;
+}
+
 /* Eq. (9): f~ = Re sum_n sum_{m=-n..n, n-m even} Z_nm R_nm(rho) exp(j m theta).
  * Only m >= 0 moments are stored; the m < 0 terms follow from
  * Z_{n,-m} = conj(Z_nm) (Sec. 2), so each m > 0 pair contributes

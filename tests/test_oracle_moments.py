@@ -1,11 +1,13 @@
-"""Pins for the oracle's moments (eq. (1), eq. (14)), resampler, reconstruction
-(eq. (9)) and error measure (eq. (13)).
+"""Pins for the oracle's moments (eq. (1), eq. (14)), the Cartesian pixel sum
+(eq. (6)), resampler, reconstruction (eq. (9)) and error measures (eq. (12),
+(13)).
 
 The checks use closed forms (constant and linear frames), exact symmetry laws
 of eq. (1) (rotation / flip phase laws, conjugate symmetry of Sec. 2),
 orthogonality on Gauss-Legendre rings, linearity, and the Neumann factor of
 eq. (15) as an exact halving of m = 0.
 """
+import math
 from fractions import Fraction
 
 import numpy as np
@@ -207,3 +209,45 @@ def test_recon_error_eq13():
     r = oracle.recon_error(f, 0.5 * f, mask)
     # every non-zero pixel is off by half of itself: 2 pixels x 1/4
     assert abs(r["eps12"] - 0.5) < 1e-15 and r["zeros"] == 1
+
+
+def _disk_sums(N):
+    # integer pixel-centre coordinates X = 2j - (N-1), Y = (N-1) - 2i (units of half a pixel)
+    X = 2 * np.arange(N, dtype=np.int64) - (N - 1)
+    Y = (N - 1) - 2 * np.arange(N, dtype=np.int64)
+    XX, YY = np.meshgrid(X, Y)
+    inside = XX * XX + YY * YY <= N * N
+    return XX, YY, inside
+
+
+@pytest.mark.parametrize("N", [16, 17])
+def test_cartesian_moment_closed_forms(N):
+    # eq. (6) with Delta = 2/N on the unit disk: closed forms from integer pixel sums
+    XX, YY, inside = _disk_sums(N)
+    d2 = (2.0 / N) ** 2
+    cnt = int(inside.sum())
+    one = inside.astype(np.float64)
+    z00 = oracle.cartesian_moment(one, 0, 0)
+    assert abs(z00 - d2 * cnt / math.pi) <= 1e-14 * abs(z00)
+    assert abs(oracle.cartesian_moment(one, 0, 0, neumann=True) - z00 / 2) <= 1e-15
+    # R_20 = 2 rho^2 - 1, rho^2 = P / N^2
+    sP = int((XX * XX + YY * YY)[inside].sum())
+    z20 = oracle.cartesian_moment(one, 2, 0)
+    assert abs(z20 - 3.0 / math.pi * d2 * (2.0 * sP / N ** 2 - cnt)) <= 1e-13
+    # rho e^{-j theta} = (X - jY) / N: the x and y coordinate images give
+    # Z_11 = (2/pi) Delta^2 sum X^2 / N^2 and -j (2/pi) Delta^2 sum Y^2 / N^2
+    sX2 = int((XX * XX)[inside].sum())
+    zx = oracle.cartesian_moment(np.where(inside, XX / N, 0.0), 1, 1)
+    zy = oracle.cartesian_moment(np.where(inside, YY / N, 0.0), 1, 1)
+    ref = 2.0 / math.pi * d2 * sX2 / N ** 2
+    assert abs(zx - ref) <= 1e-13 * ref and abs(zy + 1j * ref) <= 1e-13 * ref
+
+
+@pytest.mark.parametrize("N", [12, 13])
+def test_cartesian_moment_quarter_turn(N):
+    # rotating the content a quarter turn counter-clockwise multiplies Z_nm by (-j)^m
+    f = np.random.default_rng(N).normal(size=(N, N))
+    for n, m in [(1, 1), (2, 2), (3, 1), (5, 3), (8, 4), (6, 0)]:
+        z = oracle.cartesian_moment(f, n, m)
+        zr = oracle.cartesian_moment(np.rot90(f), n, m)
+        assert abs(zr - z * (-1j) ** m) <= 1e-12 * (1 + abs(z)), (n, m)
