@@ -241,6 +241,24 @@ zm_status zm_recon_error(zm_plan_t plan, const void* d_ref, const void* d_recon,
 zm_status zm_pad_size(int n, int* size, int* offset);
 zm_status zm_embed(const void* d_src, int n, int batch, void* d_dst, int is_double, zm_stream_t stream);
 
+/* One moment Z_nm of `batch` square n_side x n_side FP32 frames (frame b at
+ * d_frames + b * frame_stride elements, frame_stride >= n_side^2) by the
+ * Cartesian pixel sum of eq. (6), every disk pixel centre weighted by
+ * Delta^2 = (2 / n_side)^2, divided by the Neumann factor of eq. (15) when
+ * `neumann` is set (eq. (14)); the constant follows eq. (1) (a constant
+ * disk gives Z_00 = value * (disk pixels) Delta^2 / pi).  The 8-point
+ * symmetry of the grid evaluates R_nm once per orbit of 8 pixels (Sec. 2;
+ * Fig. 5 times one moment of any order this way).  0 <= n <= 500,
+ * |m| <= n, n - |m| even (m < 0 returns conj(Z_n|m|), Sec. 2).  d_out
+ * (device) receives batch pairs (re, im) in FP64; FP64 accumulation with a
+ * fixed reduction order.  d_ws is a device workspace of at least
+ * zm_cartesian_workspace_size(n_side, batch) bytes.  Runs on the calling
+ * thread's current device, asynchronously on `stream`.  Errors: ZM_EINVAL
+ * for bad arguments, ZM_EDEVICE for launch failures. */
+zm_status zm_cartesian_workspace_size(int n_side, int batch, size_t* bytes);
+zm_status zm_moment_cartesian(const void* d_frames, int n_side, int batch, long long frame_stride, int n, int m,
+                              int neumann, double* d_out, void* d_ws, size_t ws_bytes, zm_stream_t stream);
+
 zm_status zm_destroy(zm_plan_t plan);
 
 const char* zm_status_str(zm_status s);

@@ -85,6 +85,9 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_sz)]),
     "zm_batch_destroy": (ctypes.c_int, [_vp]),
     "zm_moments_batch": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp]),
+    "zm_cartesian_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_sz)]),
+    "zm_moment_cartesian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
+                                           ctypes.c_int, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "zm_destroy": (ctypes.c_int, [_vp]),
     "zm_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "zm_last_error": (ctypes.c_char_p, []),
@@ -138,6 +141,33 @@ def embed(frames, stream=None):
     _check(_lib.zm_embed(_vp(frames.data_ptr()), n, B, _vp(out.data_ptr()), int(frames.dtype == torch.float64),
                          _stream_handle(stream)), "zm_embed")
     return out
+
+
+def moment_cartesian(frames, n: int, m: int, neumann: bool = False, workspace=None, stream=None):
+    """One moment Z_nm of each of [B, N, N] (or [N, N]) float32 CUDA frames by
+    the Cartesian pixel sum of eq. (6) (eq. (14) with ``neumann``), using the
+    8-point symmetry of the square grid.  Returns a complex128 tensor [B]
+    (a 0-d tensor for one frame) on the frames' device."""
+    import torch
+    squeeze = frames.dim() == 2
+    if squeeze:
+        frames = frames.unsqueeze(0)
+    B, N, N2 = frames.shape
+    if N != N2:
+        raise ValueError("moment_cartesian expects square frames")
+    if frames.dtype != torch.float32 or not frames.is_cuda:
+        raise ValueError("moment_cartesian expects float32 CUDA frames")
+    frames = frames.contiguous()
+    need = _sz()
+    _check(_lib.zm_cartesian_workspace_size(N, B, ctypes.byref(need)), "zm_cartesian_workspace_size")
+    if workspace is None or workspace.numel() < need.value:
+        workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=frames.device)
+    out = torch.empty(B, 2, dtype=torch.float64, device=frames.device)
+    _check(_lib.zm_moment_cartesian(_vp(frames.data_ptr()), N, B, N * N, int(n), int(m), int(bool(neumann)),
+                                    _vp(out.data_ptr()), _vp(workspace.data_ptr()), workspace.numel(),
+                                    _stream_handle(stream)), "zm_moment_cartesian")
+    z = torch.view_as_complex(out)
+    return z[0] if squeeze else z
 
 
 def exported_symbols():

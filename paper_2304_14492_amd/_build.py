@@ -13,7 +13,8 @@ INCLUDE = os.path.join(ROOT, "include")
 OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzm.so")
 
-SOURCES = ["plan.cpp", "zrp_table.hip", "polar_fft.hip", "project.hip", "reconstruct.hip", "batch.hip"]
+SOURCES = ["plan.cpp", "zrp_table.hip", "polar_fft.hip", "project.hip", "reconstruct.hip", "batch.hip",
+           "cartesian.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
