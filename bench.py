@@ -248,6 +248,38 @@ def reconstruction(reps=3):
     return out
 
 
+def cartesian_single_moment(side=4000, reps=20):
+    """Fig. 5's workload: one moment of any order of side x side frames (the
+    figure's largest side) by the Cartesian pixel sum of eq. (6) with 8-point
+    symmetry; seeded uniform frames.  HBM bytes = the frames (4 B per pixel)."""
+    import torch
+    import paper_2304_14492_amd as zm
+    g = torch.Generator(device="cuda").manual_seed(4000)
+    runs = []
+    for B in (1, 16):
+        f = torch.rand(B, side, side, device="cuda", generator=g)
+        for n, m in ((10, 2), (200, 100), (500, 250)):
+            zm.moment_cartesian(f, n, m)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                zm.moment_cartesian(f, n, m)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            gbs = B * side * side * 4 / (ms / 1e3) / 1e9
+            runs.append({"batch": B, "n": n, "m": m, "ms_per_call": round(ms, 4),
+                         "us_per_frame": round(ms * 1e3 / B, 2), "GB_per_s": round(gbs, 1)})
+        del f
+    head = [r for r in runs if r["batch"] == 16 and r["n"] == 200][0]
+    return {"side": side, "runs": runs,
+            "roofline": {"bound": "hbm", "kernel": "cart_moment_kernel (batch 16, n 200, m 100)",
+                         "achieved": head["GB_per_s"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(head["GB_per_s"] / HBM_PEAK_GBS, 4),
+                         "bytes_per_launch": 16 * side * side * 4}}
+
+
 def serving(dtype, count, qps, warmup_s):
     """Serving form for one projection dtype: saturation throughput (every
     request queued at t = 0), then Poisson streams at the fixed rate `qps` and
@@ -298,6 +330,9 @@ def main():
                     help="at most this many requests per serving run (0 skips serving)")
     ap.add_argument("--no-batch-form", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction timing")
+    ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian single-moment timing")
+    ap.add_argument("--cartesian-only", action="store_true",
+                    help="only the Cartesian single-moment timing (prints its JSON object)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters into bytes")
@@ -319,6 +354,9 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_mib": args.calibrate_copy, "bytes_read_per_copy": 4 * n,
                           "bytes_written_per_copy": 4 * n}))
+        return
+    if args.cartesian_only:
+        print(json.dumps({"cartesian_single_moment": cartesian_single_moment()}), flush=True)
         return
     print(f"[bench] batch={args.batch} steps={args.steps} warmup={args.warmup} dtype={args.dtype}",
           file=sys.stderr, flush=True)
@@ -373,6 +411,10 @@ def main():
         torch.cuda.empty_cache()
         res["reconstruction"] = reconstruction()
         print(f"[bench] reconstruction: {res['reconstruction']}", file=sys.stderr, flush=True)
+    if not args.no_cartesian:
+        torch.cuda.empty_cache()
+        res["cartesian_single_moment"] = cartesian_single_moment()
+        print(f"[bench] cartesian: {res['cartesian_single_moment']['roofline']}", file=sys.stderr, flush=True)
     if args.requests > 0:
         torch.cuda.empty_cache()
         res["latency"] = {}

@@ -19,7 +19,8 @@
 // Layout: a workgroup owns a 32 x 32 tile of first-octant orbits (quadrant
 // indices u >= v) of one frame and stages the tile's eight mirror blocks in
 // LDS with row-contiguous loads (all of a thread's loads in flight before the
-// first LDS write), so the transposed members (+-Y, +-X) are not gathered
+// first LDS write; the tile grid is shifted so that tile columns start on
+// 128-byte lines), so the transposed members (+-Y, +-X) are not gathered
 // down columns.  Each thread's 4 orbits share one pass of the recurrence.
 // Partial sums per tile, then a fixed-order reduction per frame: results do
 // not depend on timing.
@@ -58,7 +59,10 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
     while ((tu + 1) * (tu + 2) / 2 <= t) ++tu;
     while (tu * (tu + 1) / 2 > t) --tu;
     const int tv = t - tu * (tu + 1) / 2;
-    const int u0 = tu * kT, v0 = tv * kT;
+    // the tile grid starts sh indices before u = 0 so that tile columns begin
+    // on 128-byte lines (the +X column of index u is c0 + u)
+    const int c0 = odd ? (N - 1) / 2 : N / 2, sh = c0 % kT;
+    const int u0 = tu * kT - sh, v0 = tv * kT - sh;
     const int K = (n - m) / 2;
     for (int k = 1 + tid; k <= K; k += kThreads) {
         const double kk = k, am = m;
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
         const int s = e / (kT * kT), a = (e / kT) % kT, c = e % kT;
         const int ri = (s < 4 ? v0 : u0) + a, ci = (s < 4 ? u0 : v0) + c;
         vals[i] = 0.f;
-        if (ri < Q && ci < Q) {
+        if (ri >= 0 && ci >= 0 && ri < Q && ci < Q) {
             const int row = (s & 1) ? N - 1 - row_p(ri, N, odd) : row_p(ri, N, odd);
             const int col = (s & 2) ? N - 1 - col_p(ci, N, odd) : col_p(ci, N, odd);
             vals[i] = f[(size_t)row * N + col];
@@ -117,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
         const int ul = tid % kT, vl = tid / kT + (kThreads / kT) * e;
         const int u = u0 + ul, v = v0 + vl;
         const long X = xval(u, odd), Y = xval(v, odd), P = X * X + Y * Y;
-        const bool in = u < Q && v <= u && P <= (long)N * N;
+        const bool in = v >= 0 && u < Q && v <= u && P <= (long)N * N;
         const double fXY = blk[0][vl][ul], fXmY = blk[1][vl][ul], fmXY = blk[2][vl][ul], fmXmY = blk[3][vl][ul];
         const double fYX = blk[4][ul][vl], fYmX = blk[5][ul][vl], fmYX = blk[6][ul][vl], fmYmX = blk[7][ul][vl];
         // j^m a + (-j)^m c = jr (a + c) + j ji (a - c)
@@ -208,7 +212,8 @@ __global__ __launch_bounds__(kThreads) void cart_final_kernel(const double* __re
 
 int tiles_of(int N) {
     const int Q = (N & 1) ? (N + 1) / 2 : N / 2;
-    const int T = (Q + kT - 1) / kT;
+    const int sh = ((N & 1) ? (N - 1) / 2 : N / 2) % kT;  // grid shift of the kernel
+    const int T = (Q + sh + kT - 1) / kT;
     return T * (T + 1) / 2;
 }
 
