@@ -280,6 +280,28 @@ def cartesian_single_moment(side=4000, reps=20):
                          "bytes_per_launch": 16 * side * side * 4}}
 
 
+def dedup_throughput(side=256, n_distinct=700, reps=3):
+    """Sec. 2.7: duplicate groups of a synthetic set of side x side frames
+    (the paper's image side): n_distinct originals, about half of them with
+    copies, quarter / half turns and mirror images.  Moments to order 20 on
+    the GPU (256 frames per launch), hashes at orders 16 and 20."""
+    import torch
+    import synth
+    from paper_2304_14492_amd import Plan, dedup
+    frames, truth = synth.dedup_set(side, n_distinct=n_distinct, seed=900)
+    dev = torch.from_numpy(np.stack(frames)).cuda()
+    plan = Plan(20, side, side, dtype="f32")
+    groups, _ = dedup.find_duplicates(dev, orders=(16, 20), plan=plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        groups, _ = dedup.find_duplicates(dev, orders=(16, 20), plan=plan)
+    dt = (time.perf_counter() - t0) / reps
+    return {"frames": len(frames), "side": side, "orders": [16, 20], "seconds": round(dt, 4),
+            "frames_per_s": round(len(frames) / dt, 1), "groups_found": len(groups),
+            "groups_planted": len(truth), "all_found": groups == truth}
+
+
 def serving(dtype, count, qps, warmup_s):
     """Serving form for one projection dtype: saturation throughput (every
     request queued at t = 0), then Poisson streams at the fixed rate `qps` and
@@ -331,6 +353,7 @@ def main():
     ap.add_argument("--no-batch-form", action="store_true")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction timing")
     ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian single-moment timing")
+    ap.add_argument("--no-dedup", action="store_true", help="skip the de-duplication timing")
     ap.add_argument("--cartesian-only", action="store_true",
                     help="only the Cartesian single-moment timing (prints its JSON object)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -415,6 +438,10 @@ def main():
         torch.cuda.empty_cache()
         res["cartesian_single_moment"] = cartesian_single_moment()
         print(f"[bench] cartesian: {res['cartesian_single_moment']['roofline']}", file=sys.stderr, flush=True)
+    if not args.no_dedup:
+        torch.cuda.empty_cache()
+        res["dedup"] = dedup_throughput()
+        print(f"[bench] dedup: {res['dedup']}", file=sys.stderr, flush=True)
     if args.requests > 0:
         torch.cuda.empty_cache()
         res["latency"] = {}

@@ -335,3 +335,48 @@ def minmax(ft: np.ndarray, f: np.ndarray, mask: np.ndarray) -> np.ndarray:
     scale = (hi - lo) / (hi_t - lo_t) if hi_t > lo_t else 0.0
     out[mask] = (ft[mask] - lo_t) * scale + lo
     return out
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.7, eq. (16)-(17): moments as image hashes for de-duplication.
+# ---------------------------------------------------------------------------
+def dedup_groups(Z: np.ndarray, nmax: int, orders, rtol: float):
+    """Groups of images with the same content, from their moment vectors Z
+    ([K][M_tot] complex, canonical order, moments up to nmax).  For each order
+    l in ``orders`` (eq. (16)) an image's hash is the vector of magnitudes
+    |Z_lm|, m = l mod 2 .. l step 2 (unchanged by quarter turns and mirrors
+    of the content); two images agree at order l when the hashes differ by at
+    most rtol times the larger one's largest entry (max norm).  eq. (17): two
+    images have the same content when they agree at every listed order; the
+    groups are the classes of that relation closed transitively.  All pairs
+    are compared (small sets).  Returns sorted lists of >= 2 indices."""
+    K = len(Z)
+    idx = {(n, m): i for i, (n, m) in enumerate(pairs(nmax))}
+    hashes = []
+    for k in range(K):
+        hk = []
+        for l in orders:
+            hk.append([abs(Z[k][idx[(l, m)]]) for m in range(l % 2, l + 1, 2)])
+        hashes.append(hk)
+    parent = list(range(K))
+
+    def root(a):
+        while parent[a] != a:
+            a = parent[a]
+        return a
+
+    for i in range(K):
+        for j in range(i + 1, K):
+            same = True
+            for o in range(len(orders)):
+                a, b = hashes[i][o], hashes[j][o]
+                scale = max(max(a), max(b))
+                if max(abs(x - y) for x, y in zip(a, b)) > rtol * scale:
+                    same = False
+                    break
+            if same:
+                parent[root(j)] = root(i)
+    classes = {}
+    for k in range(K):
+        classes.setdefault(root(k), []).append(k)
+    return sorted(sorted(c) for c in classes.values() if len(c) > 1)

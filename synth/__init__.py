@@ -11,4 +11,5 @@ from .frames import (  # noqa: F401
     config_frame,
     batch_sides,
     request_stream,
+    dedup_set,
 )

@@ -154,3 +154,29 @@ def request_stream(count: int, qps: float, seed: int = 5):
         H, W, _ = SERVE_SIZES[kinds[i]]
         out.append((float(t[i]), H, W, int(nm[i]), 5000 + i))
     return out
+
+
+def dedup_set(side: int, n_distinct: int = 5, seed: int = 31):
+    """A synthetic image set with planted duplicates (stands in for a computer
+    vision dataset with repeated images, Sec. 2.7).  Original k (seed + k,
+    blob + polygon content, zero outside the disk) is followed by its planted
+    variants, each an exact pixel permutation of the original that keeps the
+    content: a copy, a quarter turn, a half turn and a left-right mirror for
+    even k; a copy only for odd k.  One more frame is original 0 shifted by
+    one pixel (different content at the pixel level: must not be grouped).
+    Returns (frames, groups): groups lists the indices of each original and
+    its variants, in order."""
+    frames, groups = [], []
+    spec = FrameSpec(side, side, blobs=6, polygons=3, noise=False, zero_outside=True)
+    for k in range(n_distinct):
+        f = make_frame(spec, seed + k)
+        members = [len(frames)]
+        frames.append(f)
+        variants = [f.copy(), np.rot90(f, 1), np.rot90(f, 2), f[:, ::-1]] if k % 2 == 0 else [f.copy()]
+        for v in variants:
+            members.append(len(frames))
+            frames.append(np.ascontiguousarray(v))
+        groups.append(members)
+    shifted = np.roll(frames[0], 1, axis=1)
+    frames.append(np.ascontiguousarray(shifted))
+    return frames, groups
