@@ -6,7 +6,9 @@
 //   stage-2 items (plan group, 8 blocks)  -> radial projection on MFMA.
 // One persistent kernel pops items with atomic counters: stage-1 items from
 // eight ranges (one per XCD, taking from the others when its own is empty),
-// then stage-2 items.  A workgroup counts its finished stage-1 tiles and,
+// then stage-2 items; a workgroup claims its next item of its own range
+// inside the current tile's body, so the atomic overlaps the tile's first
+// loads.  A workgroup counts its finished stage-1 tiles and,
 // when it moves on to another group, to stage 2 or to the exit, releases
 // them (device-scope release fence) and adds them to the group's counter; a
 // stage-2 item waits (acquire) until its group's counter reaches the group's
@@ -51,8 +53,9 @@ constexpr bool batch_variant_ok() {
     return A2 * 2 <= A && FftLds<float, A, A2>::bytes <= 80 * 1024;  // two workgroups per CU
 }
 
-// a stage-1 item covers max(kItemPairs, P) ring pairs of one frame (several
-// rounds of the FFT body when P < kItemPairs)
+// a stage-1 item covers max(kItemPairs, P) ring pairs of one frame: with 1,
+// one round of the FFT body, the standalone kernel's tile (more rounds per
+// item were measured slower: fewer radial neighbours in flight per XCD)
 constexpr int kItemPairs = 1;
 
 template <int AI, int A2I>
