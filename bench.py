@@ -356,6 +356,10 @@ def main():
     ap.add_argument("--no-dedup", action="store_true", help="skip the de-duplication timing")
     ap.add_argument("--cartesian-only", action="store_true",
                     help="only the Cartesian single-moment timing (prints its JSON object)")
+    ap.add_argument("--batch-form-only", action="store_true",
+                    help="only the batched persistent form's timing (prints its JSON object)")
+    ap.add_argument("--recon-only", action="store_true",
+                    help="only the reconstruction timing (prints its JSON object)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times): the reference for scaling "
                          "the FETCH_SIZE / WRITE_SIZE counters into bytes")
@@ -380,6 +384,12 @@ def main():
         return
     if args.cartesian_only:
         print(json.dumps({"cartesian_single_moment": cartesian_single_moment()}), flush=True)
+        return
+    if args.batch_form_only:
+        print(json.dumps({"batch_form": batch_form(args.steps)}), flush=True)
+        return
+    if args.recon_only:
+        print(json.dumps({"reconstruction": reconstruction()}), flush=True)
         return
     print(f"[bench] batch={args.batch} steps={args.steps} warmup={args.warmup} dtype={args.dtype}",
           file=sys.stderr, flush=True)
