@@ -47,7 +47,7 @@ __device__ __forceinline__ int col_p(int u, int N, int odd) { return odd ? (N - 
 __device__ __forceinline__ int row_p(int v, int N, int odd) { return odd ? (N - 1) / 2 - v : N / 2 - 1 - v; }
 
 __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __restrict__ img, long long stride, int N,
-                                                               int n, int m, double* __restrict__ part) {
+                                                               int n, int m, int vec, double* __restrict__ part) {
     __shared__ float blk[8][kT][kT + 1];
     __shared__ double cf[kMaxK][3];  // (alpha, beta, gamma) of step k, (-1)^k folded in
     __shared__ double red[2][kThreads];
@@ -86,24 +86,58 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
     // bit 0 of the block: the row's coordinate negated; bit 1: the column's
     const float* f = img + (size_t)b * (size_t)stride;
     // all of a thread's loads are issued before any is written to LDS
-    constexpr int kPer = 8 * kT * kT / kThreads;
-    float vals[kPer];
+    if (vec) {
+        // 16-byte loads (N and the frame stride multiples of 4): with the grid
+        // shift, the +X columns of a tile row start at a multiple of 32 and
+        // the -X columns end just below one, so a tile row is 8 aligned float4
+        // that lie wholly inside or wholly outside the frame; the -X pieces
+        // come in descending column order
+        constexpr int kPer4 = 8 * kT * (kT / 4) / kThreads;
+        float4 v4[kPer4];
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const int e = tid + kThreads * i;
-        const int s = e / (kT * kT), a = (e / kT) % kT, c = e % kT;
-        const int ri = (s < 4 ? v0 : u0) + a, ci = (s < 4 ? u0 : v0) + c;
-        vals[i] = 0.f;
-        if (ri >= 0 && ci >= 0 && ri < Q && ci < Q) {
-            const int row = (s & 1) ? N - 1 - row_p(ri, N, odd) : row_p(ri, N, odd);
-            const int col = (s & 2) ? N - 1 - col_p(ci, N, odd) : col_p(ci, N, odd);
-            vals[i] = f[(size_t)row * N + col];
+        for (int i = 0; i < kPer4; ++i) {
+            const int e = tid + kThreads * i;
+            const int s = e / (kT * kT / 4), a = (e / (kT / 4)) % kT, q = e % (kT / 4);
+            const int ri = (s < 4 ? v0 : u0) + a, ci0 = s < 4 ? u0 : v0;
+            const int base = (s & 2) ? N - kT - (c0 + ci0) + 4 * q : c0 + ci0 + 4 * q;  // first column of the piece
+            v4[i] = float4{0.f, 0.f, 0.f, 0.f};
+            if (ri >= 0 && ri < Q && base >= 0 && base + 3 <= N - 1) {
+                const int row = (s & 1) ? N - 1 - row_p(ri, N, odd) : row_p(ri, N, odd);
+                v4[i] = *reinterpret_cast<const float4*>(f + (size_t)row * N + base);
+            }
         }
-    }
 #pragma unroll
-    for (int i = 0; i < kPer; ++i) {
-        const int e = tid + kThreads * i;
-        blk[e / (kT * kT)][(e / kT) % kT][e % kT] = vals[i];
+        for (int i = 0; i < kPer4; ++i) {
+            const int e = tid + kThreads * i;
+            const int s = e / (kT * kT / 4), a = (e / (kT / 4)) % kT, q = e % (kT / 4);
+            const int ci0 = s < 4 ? u0 : v0;
+            const float w[4] = {v4[i].x, v4[i].y, v4[i].z, v4[i].w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int c = (s & 2) ? kT - 1 - 4 * q - j : 4 * q + j;  // tile column of element j
+                blk[s][a][c] = ci0 + c >= 0 ? w[j] : 0.f;  // indices below 0 belong to the other side
+            }
+        }
+    } else {
+        constexpr int kPer = 8 * kT * kT / kThreads;
+        float vals[kPer];
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = tid + kThreads * i;
+            const int s = e / (kT * kT), a = (e / kT) % kT, c = e % kT;
+            const int ri = (s < 4 ? v0 : u0) + a, ci = (s < 4 ? u0 : v0) + c;
+            vals[i] = 0.f;
+            if (ri >= 0 && ci >= 0 && ri < Q && ci < Q) {
+                const int row = (s & 1) ? N - 1 - row_p(ri, N, odd) : row_p(ri, N, odd);
+                const int col = (s & 2) ? N - 1 - col_p(ci, N, odd) : col_p(ci, N, odd);
+                vals[i] = f[(size_t)row * N + col];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kPer; ++i) {
+            const int e = tid + kThreads * i;
+            blk[e / (kT * kT)][(e / kT) % kT][e % kT] = vals[i];
+        }
     }
     __syncthreads();
 
@@ -245,8 +279,10 @@ zm_status zm_moment_cartesian(const void* d_frames, int n_side, int batch, long 
         return fail(ZM_EINVAL, "null pointer or workspace smaller than zm_cartesian_workspace_size");
     hipStream_t s = (hipStream_t)stream;
     const int ntiles = tiles_of(n_side);
+    // 16-byte loads when every frame row starts 16-byte aligned
+    const int vec = (n_side % 4 == 0 && frame_stride % 4 == 0 && ((uintptr_t)d_frames & 15) == 0) ? 1 : 0;
     hipLaunchKernelGGL(cart_moment_kernel, dim3(ntiles, batch), dim3(kThreads), 0, s, (const float*)d_frames,
-                       frame_stride, n_side, n, am, (double*)d_ws);
+                       frame_stride, n_side, n, am, vec, (double*)d_ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "Cartesian moment kernel launch");
     const double eps = (neumann && am == 0) ? 2.0 : 1.0;
