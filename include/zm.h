@@ -187,8 +187,11 @@ zm_status zm_batch_run(zm_batch_t batch, zm_stream_t stream);
 /* Point the batch at new frames / outputs (same plans, same order); waits for
  * the device to be idle first. */
 zm_status zm_batch_update(zm_batch_t batch, const zm_job* jobs, int njobs);
-/* Synchronise the device and report ZM_EDEVICE if a stage-2 item ever waited
- * past its bound (a failed dependency; never expected). */
+/* Synchronise the device and report ZM_EDEVICE if a stage-2 item of the last
+ * run waited past its bound (a failed dependency; never expected).  The bound
+ * is 2^24 polls (each after a short sleep); the environment variable
+ * ZM_BATCH_SPIN_LIMIT, read by zm_batch_create, replaces it (a small value
+ * exercises this error path in tests; the kernel still finishes normally). */
 zm_status zm_batch_check(zm_batch_t batch);
 /* Chosen persistent grid size, item order (0 = costliest tiles first, 1 = natural),
  * queue length and device bytes owned by the batch (any pointer may be NULL). */

@@ -614,6 +614,13 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
     zm_batch_s* b = new zm_batch_s();
     b->njobs = njobs;
     b->device = jobs[0].plan ? jobs[0].plan->device : 0;
+    if (const char* sl = std::getenv("ZM_BATCH_SPIN_LIMIT")) {
+        // bound on a stage-2 item's wait, in polls; a small value exercises
+        // the error path of a dependency that does not complete in time
+        char* end = nullptr;
+        const unsigned long v = std::strtoul(sl, &end, 10);
+        if (end != sl && *end == '\0' && v <= 0xffffffffUL) b->spin_limit = (unsigned)v;
+    }
     std::map<zm_plan_t, int> gid;
     std::vector<std::vector<int>> members;
     for (int i = 0; i < njobs; ++i) {

@@ -124,6 +124,32 @@ def test_batch_fewer_tiles_than_ranges(zm, specs):
     b.close()
 
 
+def test_batch_wait_bound_reports_error(zm, monkeypatch):
+    # Failure handling forced from the host: with a bound of 0 polls, the
+    # first projection item that finds its group's tiles still running stops
+    # waiting and raises the error flag (the kernel finishes normally).  One
+    # 4K frame has 540 tiles over 512 workgroups, so projection items start
+    # while the last tiles run.
+    monkeypatch.setenv("ZM_BATCH_SPIN_LIMIT", "0")
+    plan = zm.Plan(200, 2160, 3840, dtype="f32", rings=1080, angles=4096)
+    f = torch.rand(2160, 3840, device="cuda")
+    b = zm.Batch([plan], [f], graph=False)
+    b.run()
+    with pytest.raises(zm.ZmError) as e:
+        b.check()
+    assert e.value.status == zm.ZM_EDEVICE
+    b.close()
+    # with the default bound the same batch is fine
+    monkeypatch.delenv("ZM_BATCH_SPIN_LIMIT")
+    b = zm.Batch([plan], [f], graph=False)
+    b.run()
+    b.check()
+    ref = plan.moments(f)
+    torch.cuda.synchronize()
+    assert torch.equal(b.outs[0], ref)
+    b.close()
+
+
 def test_batch_rejects_unsupported(zm):
     f = torch.zeros(64, 64, device="cuda", dtype=torch.float64)
     p = zm.Plan(10, 64, 64, dtype="f64")
