@@ -12,6 +12,13 @@ Typical use::
     frames = torch.rand(8, 2160, 3840, device="cuda")
     Z = plan.moments(frames)            # [8, num_moments, 2] float32 (re, im)
     Zc = zm.as_complex(Z)               # complex view, canonical (n, m) order
+
+Also here: ``Batch`` / ``moments_batch`` (frames of mixed sizes and orders in
+one persistent launch), ``reconstruct`` / ``recon_error`` (eq. (9), (10),
+(12), (13), min-max), ``embed`` / ``pad_size`` (Sec. 3), ``moment_cartesian``
+(one moment by the Cartesian pixel sum of eq. (6) / (14) with 8-point
+symmetry); ``serve`` (continuous batching) and ``dedup`` (moment hashes,
+Sec. 2.7) are submodules.
 """
 from __future__ import annotations
 
