@@ -344,24 +344,34 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
             Real* xf_v = reinterpret_cast<Real*>(xbuf + (ri_v >> 1) * XSZ) + (ri_v & 1);
             // With NTHR / 4 a multiple of RPR the H ring of a thread is the same
             // in every iteration, and the H angles of a wave are its V angles:
-            // the radius is loaded once and (cos, sin) is passed across lanes.
+            // radius and (cos, sin) are passed across lanes (lane
+            // RPR * (lane / RPR) + ri holds ring ri).
             constexpr bool kHFixed = (NTHR / 4) % S::RPR == 0 && S::RPR <= 16;
             const int ri_h0 = (tid >> 2) % S::RPR;
-            const double sr_h0 = rbase + ri_h0 < R ? spx[rbase + ri_h0] : 0.0;
+            const double sr_h0 = kHFixed ? __shfl(sr_v, ((tid & 63) & ~(S::RPR - 1)) + ri_h0, 64)
+                                         : (rbase + ri_h0 < R ? spx[rbase + ri_h0] : 0.0);
+            // The V base angle advances by NTHR / RPR = A / 32 per iteration:
+            // one (cos, sin) per thread, rotated by the wave-uniform (cos, sin)
+            // of 2 pi i / 32 (one rounded product per iteration, no recurrence).
+            constexpr int kStep = NTHR / S::RPR;
+            static_assert(NTHR % S::RPR == 0 && 32 * kStep == A, "base angles step by A / 32");
+            const int a_v0 = tid / S::RPR;
+            const double c0 = trig[2 * a_v0], s0 = trig[2 * a_v0 + 1];
             __syncthreads();  // previous round's phase-3 readers are done
 #pragma unroll 2
             for (int i = 0; i < 8; ++i) {
-                const int a_v = (tid + NTHR * i) / S::RPR;  // base angle, < A / 4
+                const int a_v = a_v0 + kStep * i;  // base angle, < A / 4
                 const int rest = (tid + NTHR * i) >> 2;
                 const int ri_h = kHFixed ? ri_h0 : rest % S::RPR;
                 const int a_h = (rest / S::RPR) * 4 + (tid & 3);
                 const double sr_h = kHFixed ? sr_h0 : (rbase + ri_h < R ? spx[rbase + ri_h] : 0.0);
-                const double cv = trig[2 * a_v], sv = trig[2 * a_v + 1];
+                const double ci = trig[2 * kStep * i], si = trig[2 * kStep * i + 1];
+                const double cv = c0 * ci - s0 * si, sv = s0 * ci + c0 * si;
                 double ch, sh;
                 if constexpr (kHFixed) {
                     // lane RPR * k of the wave holds V angle (first V angle of the wave) + k
-                    const int a_v0 = (tid - (tid & 63) + NTHR * i) / S::RPR;
-                    const int src = (tid & ~63) + S::RPR * (a_h - a_v0);
+                    const int a_w0 = (tid - (tid & 63) + NTHR * i) / S::RPR;
+                    const int src = (tid & ~63) + S::RPR * (a_h - a_w0);
                     ch = __shfl(cv, src & 63, 64);
                     sh = __shfl(sv, src & 63, 64);
                 } else {
