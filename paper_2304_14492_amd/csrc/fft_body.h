@@ -328,14 +328,16 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
             // Gather the 2P rings of this round into LDS.  A wave instruction
             // covers a compact patch of 2P rings x 64/2P consecutive angles.
             // The texture path coalesces within groups of 4 lanes, so the
-            // lanes of a group should read neighbouring pixels of one row:
-            // where the ring runs vertically (angle within 45 deg of the x
-            // axis) the 4 lanes take 4 consecutive rings at one angle ("V"),
-            // where it runs horizontally 4 consecutive angles of one ring
-            // ("H").  Both lane maps cover the same patch.  Each thread works
-            // on base angles in the first quadrant; the other 3 quarter turns
-            // are exact rotations, and turns 0, 2 and turns 1, 3 fall in
-            // opposite kinds of octant.
+            // lanes of a group should read neighbouring pixels of one row.
+            // Two lane maps cover the same patch: 4 consecutive rings at one
+            // angle ("V", spread along the radius) and 4 consecutive angles of
+            // one ring ("H", spread along the ring).  At angle phi from the x
+            // axis a V group spans rows in proportion to dr sin(phi) and an H
+            // group to ds cos(phi), with dr the ring step and ds = 2 pi r / A
+            // the arc step, so V is used where tan(phi) < ds / dr.  Each
+            // thread works on base angles in the first quadrant; the other 3
+            // quarter turns are exact rotations: turns 0, 2 sit at angle phi =
+            // base angle from the x axis, turns 1, 3 at its complement.
             const int rbase = r0 + rd * S::RPR;
             const int last = min(rbase + S::RPR, R) - 1;
             const bool check = (last >= rbase) && spx[last] >= safe_s;
@@ -350,6 +352,25 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
             const int ri_h0 = (tid >> 2) % S::RPR;
             const double sr_h0 = kHFixed ? __shfl(sr_v, ((tid & 63) & ~(S::RPR - 1)) + ri_h0, 64)
                                          : (rbase + ri_h0 < R ? spx[rbase + ri_h0] : 0.0);
+            // Iteration i holds base angles in [i, i + 1) pi / 16; kv counts
+            // the iterations whose mid angle has tan below ds / dr at this
+            // round's first ring.  Turns 0, 2 of iteration i use V when
+            // i < kv, turns 1, 3 when 7 - i < kv.  kv = 4 is the octant split,
+            // the only choice without kHFixed: the two maps then cover the
+            // same samples over iterations 0..3 and 4..7 but not per iteration.
+            int kv = 4;
+            if (kHFixed && R > 1 && rbase < R) {
+                const int rn = rbase + 1 < R ? rbase + 1 : rbase - 1;
+                const double dr = fabs(spx[rn] - spx[rbase]);
+                const double ratio = 6.283185307179586 * spx[rbase] / ((double)A * dr);
+                // tan(pi (2 j + 1) / 32), j = 0..7
+                constexpr double kTanMid[8] = {0.09849140335716425, 0.3033466836073424, 0.5345111359507916,
+                                               0.8206787908286602,  1.2185035255879764, 1.8708684117893888,
+                                               3.296558208938321,   10.153170387608842};
+                kv = 0;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) kv += kTanMid[j] < ratio ? 1 : 0;
+            }
             // The V base angle advances by NTHR / RPR = A / 32 per iteration:
             // one (cos, sin) per thread, rotated by the wave-uniform (cos, sin)
             // of 2 pi i / 32 (one rounded product per iteration, no recurrence).
@@ -378,14 +399,13 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
                     ch = trig[2 * a_h];
                     sh = trig[2 * a_h + 1];
                 }
-                // iterations 0..3 hold the base angles below A / 8 (both lane maps)
-                const bool low = i < 4;
                 // turns 0, 2 use (ring, angle) p; turns 1, 3 use q
-                const int ri_p = low ? ri_v : ri_h, a_p = low ? a_v : a_h;
-                const int ri_q = low ? ri_h : ri_v, a_q = low ? a_h : a_v;
-                const double sr_p = low ? sr_v : sr_h, sr_q = low ? sr_h : sr_v;
-                const double pc = sr_p * (low ? cv : ch), ps = sr_p * (low ? sv : sh);
-                const double qc = sr_q * (low ? ch : cv), qs = sr_q * (low ? sh : sv);
+                const bool p_v = i < kv, q_v = i >= 8 - kv;
+                const int ri_p = p_v ? ri_v : ri_h, a_p = p_v ? a_v : a_h;
+                const int ri_q = q_v ? ri_v : ri_h, a_q = q_v ? a_v : a_h;
+                const double sr_p = p_v ? sr_v : sr_h, sr_q = q_v ? sr_v : sr_h;
+                const double pc = sr_p * (p_v ? cv : ch), ps = sr_p * (p_v ? sv : sh);
+                const double qc = sr_q * (q_v ? cv : ch), qs = sr_q * (q_v ? sv : sh);
                 // the four quarter turns of (c, s): x = cx + (c, -s, -c, s), y = cy - (s, c, -s, -c);
                 // with 2 cx = W - 1 and 2 cy = H - 1 the negated offsets are mirrors
                 const Coord<Real> xa = split_coord<Real>(cx + pc), yb = split_coord<Real>(cy + ps);
@@ -410,8 +430,8 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
                                      : (Real)0;
                 }
                 Real* xf_h = reinterpret_cast<Real*>(xbuf + (ri_h >> 1) * XSZ) + (ri_h & 1);
-                Real* xf_p = low ? xf_v : xf_h;
-                Real* xf_q = low ? xf_h : xf_v;
+                Real* xf_p = p_v ? xf_v : xf_h;
+                Real* xf_q = q_v ? xf_v : xf_h;
                 xf_p[2 * a_p] = val[0];
                 xf_q[2 * (a_q + A / 4)] = val[1];
                 xf_p[2 * (a_p + A / 2)] = val[2];
