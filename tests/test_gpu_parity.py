@@ -167,6 +167,7 @@ def test_neumann_halves_m0_on_gpu(zm):
     (200, 120, 30, 60, 256),   # ring count not a multiple of 16
     (130, 130, 63, 33, 128),   # A2 = 64, A1 = 2
     (300, 300, 7, 150, 512),   # A2 = 16, many sub-transforms
+    (1024, 1024, 20, 512, 128),  # arc step up to 25x the ring step: V lane map in every angle band
 ])
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_ragged_geometries(zm, H, W, nmax, R, A, dtype):
