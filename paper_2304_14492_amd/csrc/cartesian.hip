@@ -22,8 +22,9 @@
 // first LDS write; the tile grid is shifted so that tile columns start on
 // 128-byte lines), so the transposed members (+-Y, +-X) are not gathered
 // down columns.  Each thread's 4 orbits share one pass of the recurrence.
-// Partial sums per tile, then a fixed-order reduction per frame: results do
-// not depend on timing.
+// Tiles with no orbit inside the disk (about a fifth of them) skip their
+// loads and write a zero partial.  Partial sums per tile, then a fixed-order
+// reduction per frame: results do not depend on timing.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -37,7 +38,6 @@ using zm::hip_fail;
 
 constexpr int kT = 32;  // orbit tile side
 constexpr int kThreads = 256;
-constexpr int kMaxK = zm::kMaxTableOrder / 2 + 1;
 constexpr int kMaxSide = 32768;
 
 // quadrant index u -> doubled coordinate X (units of half a pixel), and the
@@ -49,8 +49,10 @@ __device__ __forceinline__ int row_p(int v, int N, int odd) { return odd ? (N - 
 __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __restrict__ img, long long stride, int N,
                                                                int n, int m, int vec, double* __restrict__ part) {
     __shared__ float blk[8][kT][kT + 1];
-    __shared__ double cf[kMaxK][3];  // (alpha, beta, gamma) of step k, (-1)^k folded in
-    __shared__ double red[2][kThreads];
+    __shared__ double red[2][kThreads / 64];
+    // (alpha, beta, gamma) of step k, (-1)^k folded in, k = 1..K: 3 (K + 1)
+    // doubles of dynamic LDS, so low orders leave room for more workgroups
+    extern __shared__ double cf[];
     const int tid = threadIdx.x, b = blockIdx.y;
     const int odd = N & 1, Q = odd ? (N + 1) / 2 : N / 2;
     // tile t -> (tu, tv), tv <= tu, t = tu (tu + 1) / 2 + tv
@@ -63,6 +65,19 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
     // on 128-byte lines (the +X column of index u is c0 + u)
     const int c0 = odd ? (N - 1) / 2 : N / 2, sh = c0 % kT;
     const int u0 = tu * kT - sh, v0 = tv * kT - sh;
+    // no orbit of the tile inside the disk (its corner nearest the centre is
+    // outside): no loads, a zero partial, so the reduction keeps its order
+    {
+        const long Xn = xval(max(u0, 0), odd), Yn = xval(max(v0, 0), odd);
+        if (Xn * Xn + Yn * Yn > (long)N * N) {
+            if (tid == 0) {
+                double* o = part + ((size_t)b * gridDim.x + t) * 2;
+                o[0] = 0.0;
+                o[1] = 0.0;
+            }
+            return;
+        }
+    }
     const int K = (n - m) / 2;
     for (int k = 1 + tid; k <= K; k += kThreads) {
         const double kk = k, am = m;
@@ -77,9 +92,9 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
             be = (2.0 * kk + am - 1.0) * am * am / a1;
             ga = 2.0 * (kk + am - 1.0) * (kk - 1.0) * (2.0 * kk + am) / a1;
         }
-        cf[k][0] = -al;
-        cf[k][1] = -be;
-        cf[k][2] = -ga;
+        cf[3 * k] = -al;
+        cf[3 * k + 1] = -be;
+        cf[3 * k + 2] = -ga;
     }
     // blocks 0..3: rows of +-Y (index v), columns of +-X (index u): f(+-X, +-Y) at [v][u]
     // blocks 4..7: rows of +-X (index u), columns of +-Y (index v): f(+-Y, +-X) at [u][v]
@@ -187,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
         q2[e] = 0.0;
     }
     for (int k = 1; k <= K; ++k) {
-        const double al = cf[k][0], be = cf[k][1], ga = cf[k][2];
+        const double al = cf[3 * k], be = cf[3 * k + 1], ga = cf[3 * k + 2];
 #pragma unroll
         for (int e = 0; e < kOrb; ++e) {
             const double q = (al * xs[e] + be) * q1[e] + ga * q2[e];
@@ -201,20 +216,27 @@ __global__ __launch_bounds__(kThreads) void cart_moment_kernel(const float* __re
         accr += wgt[e] * q1[e] * gr[e];
         acci += wgt[e] * q1[e] * gi[e];
     }
-    red[0][tid] = accr;
-    red[1][tid] = acci;
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if (tid < s) {
-            red[0][tid] += red[0][tid + s];
-            red[1][tid] += red[1][tid + s];
-        }
-        __syncthreads();
+    // fixed-order reduction: a butterfly within each wave, then the waves in order
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        accr += __shfl_xor(accr, o, 64);
+        acci += __shfl_xor(acci, o, 64);
     }
+    if ((tid & 63) == 0) {
+        red[0][tid >> 6] = accr;
+        red[1][tid >> 6] = acci;
+    }
+    __syncthreads();
     if (tid == 0) {
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) {
+            sr += red[0][w];
+            si += red[1][w];
+        }
         double* o = part + ((size_t)b * gridDim.x + t) * 2;
-        o[0] = red[0][0];
-        o[1] = red[1][0];
+        o[0] = sr;
+        o[1] = si;
     }
 }
 
@@ -281,8 +303,9 @@ zm_status zm_moment_cartesian(const void* d_frames, int n_side, int batch, long 
     const int ntiles = tiles_of(n_side);
     // 16-byte loads when every frame row starts 16-byte aligned
     const int vec = (n_side % 4 == 0 && frame_stride % 4 == 0 && ((uintptr_t)d_frames & 15) == 0) ? 1 : 0;
-    hipLaunchKernelGGL(cart_moment_kernel, dim3(ntiles, batch), dim3(kThreads), 0, s, (const float*)d_frames,
-                       frame_stride, n_side, n, am, vec, (double*)d_ws);
+    const size_t cf_bytes = 3 * (size_t)((n - am) / 2 + 1) * sizeof(double);
+    hipLaunchKernelGGL(cart_moment_kernel, dim3(ntiles, batch), dim3(kThreads), cf_bytes, s,
+                       (const float*)d_frames, frame_stride, n_side, n, am, vec, (double*)d_ws);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(e, "Cartesian moment kernel launch");
     const double eps = (neumann && am == 0) ? 2.0 : 1.0;
