@@ -74,52 +74,127 @@ __global__ __launch_bounds__(kThreads) void recon_polar_kernel(const ZT* __restr
 // Per m, S_m = sum_k Z_{m+2k,m} Q_k(x) with the plan's recurrence
 // coefficients (jac: alpha, beta, gamma per moment; the same for every pixel,
 // read with scalar loads), then f~ += c_m rho^m Re(S_m exp(j m theta)).
+// pixels per thread of the pixel-centre kernel: they share every read of the
+// staged coefficients, which would otherwise outrun the FP64 pipes.  A
+// workgroup covers 64 x 16 pixels, each wave a 16 x 16 tile (compact, so
+// waves wholly outside the disk skip the recurrence), each thread one column
+// of 4 pixels 4 rows apart.
+constexpr int kPix = 4;
+constexpr int kTileW = 64, kTileH = 16;
+
 template <typename ZT, typename OT>
 __global__ __launch_bounds__(kThreads) void recon_cart_kernel(const ZT* __restrict__ Zall, int Mtot, int nmax, int H,
                                                               int W, const double* __restrict__ jac, int neumann,
                                                               int one_sided, OT* __restrict__ out) {
-    const int b = blockIdx.y;
-    const long p = (long)blockIdx.x * kThreads + threadIdx.x;
-    if (p >= (long)H * W) return;
-    const int i = (int)(p / W), jx = (int)(p % W);
+    // Column m of the recurrence, staged in LDS for the whole workgroup:
+    // entry e (n = m + 2e) holds (J0, J1, J2) of step e (e >= 1) and
+    // (Re, Im) Z_nm as doubles.  Two buffers: column m + 1 is loaded into
+    // registers while column m is used, so the loads' latency is hidden.
+    static_assert(zm::kMaxTableOrder / 2 + 1 <= kThreads, "one column entry per thread");
+    __shared__ double col[2][zm::kMaxTableOrder / 2 + 1][6];
+    const int b = blockIdx.z, tid = threadIdx.x;
+    const long npx = (long)H * W;
+    const int col0 = blockIdx.x * kTileW + (tid >> 6) * 16 + (tid & 15);
+    const int row0 = blockIdx.y * kTileH + ((tid & 63) >> 4);
     const int D = min(H, W);
-    const long X = 2L * jx - (W - 1), Y = (long)(H - 1) - 2L * i;
-    const long P = X * X + Y * Y;
-    OT* o = out + (size_t)b * H * W;
-    if (P > (long)D * D) {
-        o[p] = (OT)0;
-        return;
-    }
     const ZT* Z = Zall + (size_t)b * Mtot * 2;
-    const double rho2 = (double)P / ((double)D * (double)D);
-    const double rho = sqrt(rho2);
-    const double x = 1.0 - 2.0 * rho2;
-    const double th = atan2((double)Y, (double)X);
-    const double c1 = cos(th), s1 = sin(th);
-    double cm = 1.0, sm = 0.0;  // cos, sin of m theta (complex powers of exp(i theta))
-    double rm = 1.0;            // rho^m
-    double acc = 0.0;
-    for (int m = 0; m <= nmax; ++m) {
-        int idx = zm::canon_index(m, m);
-        double sr = zre(Z, idx), si = zim(Z, idx);  // Q_0 = 1
-        double q1 = 1.0, q2 = 0.0;                    // Q_{k-1}, Q_{k-2}
-#pragma unroll 4
-        for (int n = m + 2; n <= nmax; n += 2) {
-            idx = zm::canon_index(n, m);
-            const double* J = jac + 3 * (size_t)idx;
-            const double q = (J[0] * x + J[1]) * q1 + J[2] * q2;
-            q2 = q1;
-            q1 = q;
-            sr += q * zre(Z, idx);
-            si += q * zim(Z, idx);
-        }
-        acc += coef_m(m, neumann, one_sided) * rm * (sr * cm - si * sm);
-        const double cn = cm * c1 - sm * s1, sn = sm * c1 + cm * s1;
-        cm = cn;
-        sm = sn;
-        rm *= rho;
+    // thread's pixels: (row0 + 4k, col0); pixels outside the disk run the
+    // recurrence at x = 0 (bounded) and write 0
+    double x[kPix], rho[kPix], c1[kPix], s1[kPix], cm[kPix], sm[kPix], rm[kPix], acc[kPix];
+    bool in[kPix];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < kPix; ++k) {
+        const int i = row0 + 4 * k, jx = col0;
+        const bool live = i < H && jx < W;
+        const long X = 2L * jx - (W - 1), Y = (long)(H - 1) - 2L * i;
+        const long P = X * X + Y * Y;
+        in[k] = live && P <= (long)D * D;
+        any = any || in[k];
+        const double rho2 = in[k] ? (double)P / ((double)D * (double)D) : 0.5;
+        rho[k] = in[k] ? sqrt(rho2) : 0.0;
+        x[k] = 1.0 - 2.0 * rho2;
+        const double th = in[k] ? atan2((double)Y, (double)X) : 0.0;
+        c1[k] = cos(th);
+        s1[k] = sin(th);
+        cm[k] = 1.0;  // cos, sin of m theta (complex powers of exp(i theta))
+        sm[k] = 0.0;
+        rm[k] = 1.0;  // rho^m
+        acc[k] = 0.0;
     }
-    o[p] = (OT)acc;
+    // entry e = tid of column m (nmax - m >= 2 e), loaded into registers
+    double r0 = 0.0, r1 = 0.0, r2 = 0.0, r3 = 0.0, r4 = 0.0;
+    auto fetch = [&](int m) {
+        if (2 * tid <= nmax - m) {
+            const int idx = zm::canon_index(m + 2 * tid, m);
+            if (tid > 0) {
+                r0 = jac[3 * (size_t)idx];
+                r1 = jac[3 * (size_t)idx + 1];
+                r2 = jac[3 * (size_t)idx + 2];
+            }
+            r3 = zre(Z, idx);
+            r4 = zim(Z, idx);
+        }
+    };
+    auto stage = [&](int m, int buf) {
+        if (2 * tid <= nmax - m) {
+            double* c = col[buf][tid];
+            c[0] = r0;
+            c[1] = r1;
+            c[2] = r2;
+            c[3] = r3;
+            c[4] = r4;
+        }
+    };
+    fetch(0);
+    stage(0, 0);
+    __syncthreads();
+    for (int m = 0; m <= nmax; ++m) {
+        const int cur = m & 1;
+        if (m < nmax) fetch(m + 1);
+        if (any) {
+            const double(*cc)[6] = col[cur];
+            double sr[kPix], si[kPix], q1[kPix], q2[kPix];
+#pragma unroll
+            for (int k = 0; k < kPix; ++k) {
+                sr[k] = cc[0][3];  // Q_0 = 1
+                si[k] = cc[0][4];
+                q1[k] = 1.0;  // Q_{k-1}
+                q2[k] = 0.0;  // Q_{k-2}
+            }
+            const int Km = (nmax - m) / 2;
+#pragma unroll 2
+            for (int e = 1; e <= Km; ++e) {
+                const double j0 = cc[e][0], j1 = cc[e][1], j2 = cc[e][2], zr = cc[e][3], zi = cc[e][4];
+#pragma unroll
+                for (int k = 0; k < kPix; ++k) {
+                    const double q = (j0 * x[k] + j1) * q1[k] + j2 * q2[k];
+                    q2[k] = q1[k];
+                    q1[k] = q;
+                    sr[k] += q * zr;
+                    si[k] += q * zi;
+                }
+            }
+            const double cf = coef_m(m, neumann, one_sided);
+#pragma unroll
+            for (int k = 0; k < kPix; ++k) {
+                acc[k] += cf * rm[k] * (sr[k] * cm[k] - si[k] * sm[k]);
+                const double cn = cm[k] * c1[k] - sm[k] * s1[k], sn = sm[k] * c1[k] + cm[k] * s1[k];
+                cm[k] = cn;
+                sm[k] = sn;
+                rm[k] *= rho[k];
+            }
+        }
+        // buffer cur ^ 1 was last read for column m - 1, before the previous barrier
+        if (m < nmax) stage(m + 1, cur ^ 1);
+        __syncthreads();
+    }
+    OT* o = out + (size_t)b * npx;
+#pragma unroll
+    for (int k = 0; k < kPix; ++k) {
+        const int i = row0 + 4 * k;
+        if (i < H && col0 < W) o[(long)i * W + col0] = in[k] ? (OT)acc[k] : (OT)0;
+    }
 }
 
 // eq. (13) per frame over the disk: partial sums per block, then a
@@ -301,8 +376,8 @@ hipError_t launch_recon_polar(const zm_plan_s* p, const void* Z, int batch, void
 }
 
 hipError_t launch_recon_cart(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s) {
-    const long npx = (long)p->H * p->W;
-    dim3 grid((unsigned)((npx + kThreads - 1) / kThreads), batch);
+    static_assert(kThreads == 4 * 64 && kTileW == 4 * 16 && kTileH == 4 * kPix, "4 waves of 16 x 16 pixels");
+    dim3 grid((unsigned)((p->W + kTileW - 1) / kTileW), (unsigned)((p->H + kTileH - 1) / kTileH), batch);
     if (p->dtype == ZM_F64)
         hipLaunchKernelGGL((recon_cart_kernel<double, double>), grid, dim3(kThreads), 0, s, (const double*)Z,
                            p->num_moments, p->n_max, p->H, p->W, p->d_jac, p->neumann, one_sided, (double*)out);
