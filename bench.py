@@ -367,8 +367,8 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters into bytes")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: every frame is independent (images shard with no "
-              "communication), and multi-GPU runs are not part of this build; use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: every frame is independent, so frames shard across GPUs "
+              "with no communication and the figure per GPU is the one to measure; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
