@@ -7,7 +7,8 @@ over one batch: fused resample + angular FFT (zm_spectra), then the radial
 projection on the matrix cores (zm_project).  Frames are device resident
 before the timed region starts.
 
-Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
+Prints ONE JSON line (rank 0).  Extra keys beside the standard ones (metric,
+value, unit, ms_per_step, config, ...):
   roofline       resample+FFT kernel: algorithmic bytes per launch / average
                  launch duration (HIP events on the launch stream) vs 8 TB/s;
                  traffic = HBM bytes per launch from the committed rocprofv3
@@ -24,6 +25,14 @@ Prints ONE JSON line (rank 0).  Extra keys beside the driver contract:
                  p99.9 latency (arrival -> moments in host memory), FP32 and
                  split-BF16 projection; saturation throughput from a burst,
                  then streams at the fixed rate and at 50 % / 80 % of it
+  reconstruction eq. (9) of one 4K frame at N_max 200 at the pixel centres
+                 (FP64 rate vs the FP64 vector peak) and at the polar nodes
+  cartesian_single_moment
+                 one moment of 4000 x 4000 frames by the Cartesian pixel sum
+                 (eq. (6), 8-point symmetry) at orders 10 / 200 / 500; HBM
+                 rate of the disk pixels
+  dedup          moments as image hashes (eq. (16)/(17)) over a synthetic set
+                 with planted duplicate groups
 """
 from __future__ import annotations
 
