@@ -63,6 +63,31 @@ def test_cartesian_reconstruction_matches_oracle(zm):
     assert np.max(np.abs(g32 - o32)) <= 1e-6 * np.max(np.abs(o32))
 
 
+def test_cartesian_reconstruction_full_size_sampled(zm):
+    # 3840 x 2160 FP32 plan at N_max 200, the size and launch the benchmark
+    # times: sampled pixels (centre, disk edge, random) against eq. (9) with
+    # the exact R_nm; pixels outside the disk are exactly 0
+    H, W, nmax = 2160, 3840, 200
+    D = min(H, W)
+    Z = _rand_moments(nmax, 9)
+    plan = zm.Plan(nmax, H, W, dtype="f32")
+    g = zm.reconstruct(plan, _z_tensor(Z, np.float32), kind="cartesian").cpu().numpy()
+    rng = np.random.default_rng(9)
+    ii = np.concatenate([rng.integers(0, H, 96), [H // 2, H // 2 - 1, 0, H - 1, H // 2, H // 2, 0, H - 1]])
+    jj = np.concatenate([rng.integers(0, W, 96),
+                         [W // 2, W // 2 - 1, W // 2, W // 2 - 1, W // 2 + D // 2 - 1, W // 2 - D // 2, 0, W - 1]])
+    X = 2 * jj - (W - 1)
+    Y = (H - 1) - 2 * ii
+    P = X * X + Y * Y
+    inside = P <= D * D
+    assert 40 <= inside.sum() < len(ii)
+    assert np.all(g[ii[~inside], jj[~inside]] == 0)
+    Rv = oracle.zrp_rational(oracle.pairs(nmax), P[inside].astype(np.int64), D * D)
+    o = oracle.reconstruct(Z.astype(np.complex64).astype(np.complex128), nmax, Rv,
+                           np.arctan2(Y[inside], X[inside]).astype(np.float64))
+    assert np.max(np.abs(g[ii[inside], jj[inside]] - o)) <= 1e-6 * np.max(np.abs(o))
+
+
 @pytest.mark.parametrize("n,m", [(200, 0), (200, 2), (199, 1), (200, 100), (255, 3), (180, 180)])
 def test_cartesian_high_order_basis_function(zm, n, m):
     # a single moment Z_nm = 1 reconstructs c_m R_nm(rho) cos(m theta): checks the
