@@ -111,19 +111,25 @@ def ring_grid(R: int, rule: str = "midpoint") -> dict:
     if rule == "gauss_legendre":
         x, wg = np.polynomial.legendre.leggauss(R)
         rho = 0.5 * (x + 1.0)
-        w = 0.5 * wg * rho
-        # rho_r = M_r * 2^(e_r - 53) exactly; common denominator 2^(2L)
-        mants, shifts = [], []
-        for v in rho:
-            fm, e = math.frexp(float(v))
-            M = int(fm * (1 << 53))
-            mants.append(M)
-            shifts.append(53 - e)
-        L = max(shifts)
-        ax = np.array(mants, dtype=np.uint64)
-        ash = np.array([2 * (L - s) for s in shifts], dtype=np.int32)
-        return dict(rho=rho, w=w, ax=ax, ay=ax.copy(), ash=ash, bx=1, by=1, bsh=2 * L, rule=rule)
+        return node_grid(rho, 0.5 * wg * rho, rule)
     raise ValueError(rule)
+
+
+def node_grid(rho, w, rule: str = "nodes") -> dict:
+    """A ring grid at given FP64 nodes in (0, 1] (and weights), with the exact
+    rational form of each node: rho_r = M_r 2^(e_r - 53), rho_r^2 over the
+    common denominator 2^(2L)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    mants, shifts = [], []
+    for v in rho:
+        fm, e = math.frexp(float(v))
+        mants.append(int(fm * (1 << 53)))
+        shifts.append(53 - e)
+    L = max(shifts)
+    ax = np.array(mants, dtype=np.uint64)
+    ash = np.array([2 * (L - s) for s in shifts], dtype=np.int32)
+    return dict(rho=rho, w=np.asarray(w, dtype=np.float64), ax=ax, ay=ax.copy(), ash=ash, bx=1, by=1, bsh=2 * L,
+                rule=rule)
 
 
 def zrp(plist, grid: dict) -> np.ndarray:
