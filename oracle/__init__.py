@@ -32,7 +32,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "zm_oracle.c")
-_SO = os.path.join(_HERE, "_zm_oracle.so")
+# ZM_ORACLE_SO names another build of the same C source (the sanitizer run of
+# the CPU tests loads one built with -fsanitize=address,undefined)
+_SO = os.environ.get("ZM_ORACLE_SO") or os.path.join(_HERE, "_zm_oracle.so")
 _lib_handle = None
 
 
