@@ -96,7 +96,10 @@ typedef struct {
 int zm_num_moments(int n_max);
 
 /* Canonical position of (n, m): off(n) + m/2 with off(2p) = p(p+1),
- * off(2p+1) = (p+1)^2; -1 if n < 0, m < 0, m > n or n - m odd. */
+ * off(2p+1) = (p+1)^2; -1 if n < 0, m < 0, m > n or n - m odd.  The
+ * admissible pairs are those of the radial polynomials of eq. (2) (Sec. 2:
+ * n >= 0, |m| <= n, n - |m| even); m < 0 is not stored (Z_{n,-m} =
+ * conj(Z_nm)). */
 int zm_index(int n, int m);
 
 /* Create a plan with the default polar grid (midpoint rings, R and A as in
@@ -127,25 +130,37 @@ zm_status zm_ring_nodes(zm_plan_t plan, double* rho_out, double* w_out, size_t n
 /* Bytes of device workspace zm_moments needs for `batch` frames. */
 zm_status zm_workspace_size(zm_plan_t plan, int batch, size_t* bytes);
 
-/* Moments of `batch` frames (asynchronous on `stream`).
+/* Moments of `batch` frames by eq. (1) (Sec. 2) on the plan's polar grid:
+ * the angular integral as a pruned FFT per ring of the bilinear samples
+ * (Sec. 2.5), the radial one as a sum over rings against the eq. (7)
+ * radial table (Sec. 2.1) with the quadrature weights and (n+1)/(pi eps_m)
+ * folded in (eq. (14)-(15) when the plan has the Neumann factor).
+ * Asynchronous on `stream`.
  *   d_images : device pointer, frame b at d_images + b * image_stride elements,
  *              each H x W row-major; float (FP32 dtypes) or double (ZM_F64).
  *              Only pixels within D/2 + 1.5 px of the centre are read.
  *   d_Z      : device pointer, [batch][num_moments][2] (re, im), float or double.
  *   d_ws     : device workspace of ws_bytes >= zm_workspace_size(plan, batch).
- * Overlapping calls on one plan are safe when they use distinct workspaces. */
+ * Overlapping calls on one plan are safe when they use distinct workspaces.
+ * The plan records the completion of each call (per stream) for zm_destroy.
+ * Errors: ZM_EINVAL (null pointers, batch < 0 or > 65535, image_stride <
+ * H * W, workspace too small), ZM_EUNSUPPORTED (plan beyond the moment
+ * kernels' limits), ZM_EDEVICE (launch failure). */
 zm_status zm_moments(zm_plan_t plan, const void* d_images, int batch, long long image_stride,
                      void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream);
 
 /* The two stages of zm_moments, for callers that want the ring spectra or
- * time the stages separately.  zm_spectra runs the fused resample + angular
- * FFT and leaves F_r[m] = sum_a f^(rho_r, theta_a) exp(-2 pi i m a / A) for
+ * time the stages separately.  zm_spectra runs the fused resample (Sec. 2.5)
+ * + angular FFT (the inner, angular sum of eq. (1), whose exp(-j m theta)
+ * factor the FFT evaluates for all m at once, Sec. 2) and leaves
+ * F_r[m] = sum_a f^(rho_r, theta_a) exp(-2 pi i m a / A) for
  * m = 0..n_max in the workspace (FP32, or FP64 for ZM_F64), blocked by 16
  * rings: element (frame b, ring r, m, part c: 0 = re, 1 = im) sits at
  * [b][r / 16][m][c][r % 16] over rings_padded rings; zm_project applies the
- * radial projection to the
- * spectra of a preceding zm_spectra call on the same workspace and stream.
- * zm_moments == zm_spectra followed by zm_project. */
+ * radial projection (the outer, radial sum of eq. (1) against the eq. (7)
+ * table, Sec. 2.1) to the spectra of a preceding zm_spectra call on the
+ * same workspace and stream.  zm_moments == zm_spectra followed by
+ * zm_project; arguments and errors as for zm_moments. */
 zm_status zm_spectra(zm_plan_t plan, const void* d_images, int batch, long long image_stride, void* d_ws,
                      size_t ws_bytes, zm_stream_t stream);
 zm_status zm_project(zm_plan_t plan, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream);
@@ -185,10 +200,10 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
 /* Run the batch on `stream` (asynchronous; one graph launch). */
 zm_status zm_batch_run(zm_batch_t batch, zm_stream_t stream);
 /* Point the batch at new frames / outputs (same plans, same order); waits for
- * the device to be idle first. */
+ * the batch's last run to complete first (nothing else on the device). */
 zm_status zm_batch_update(zm_batch_t batch, const zm_job* jobs, int njobs);
-/* Synchronise the device and report ZM_EDEVICE if a stage-2 item of the last
- * run waited past its bound (a failed dependency; never expected).  The bound
+/* Wait for the batch's last run and report ZM_EDEVICE if a stage-2 item of
+ * it waited past its bound (a failed dependency; never expected).  The bound
  * is 2^24 polls (each after a short sleep); the environment variable
  * ZM_BATCH_SPIN_LIMIT, read by zm_batch_create, replaces it (a small value
  * exercises this error path in tests; the kernel still finishes normally). */
@@ -196,9 +211,21 @@ zm_status zm_batch_check(zm_batch_t batch);
 /* Chosen persistent grid size, item order (0 = costliest tiles first, 1 = natural),
  * queue length and device bytes owned by the batch (any pointer may be NULL). */
 zm_status zm_batch_config(zm_batch_t batch, int* grid, int* order, int* n_items, size_t* device_bytes);
+/* Waits for the batch's last run, then frees the batch. */
 zm_status zm_batch_destroy(zm_batch_t batch);
 /* One-shot: create (no graph), run, synchronise, check, destroy. */
 zm_status zm_moments_batch(const zm_job* jobs, int njobs, zm_stream_t stream);
+/* The one-shot batch with caller-owned device memory: zm_batch_workspace_size
+ * gives the bytes the jobs need (queue, descriptors, ring spectra, counters;
+ * no device call), and zm_moments_batch_ws lays them out in d_ws (device,
+ * 256-byte aligned, ws_bytes at least that size), uploads the queue on
+ * `stream`, runs the persistent kernel there and synchronises `stream`
+ * before returning.  It allocates no device memory.  Results as
+ * zm_moments_batch (each frame bit-identical to zm_moments on it alone).
+ * Errors: ZM_EINVAL (null or misaligned workspace, too small, bad jobs),
+ * ZM_EUNSUPPORTED (a plan outside the batched form), ZM_EDEVICE. */
+zm_status zm_batch_workspace_size(const zm_job* jobs, int njobs, size_t* bytes);
+zm_status zm_moments_batch_ws(const zm_job* jobs, int njobs, void* d_ws, size_t ws_bytes, zm_stream_t stream);
 
 /* ---- Reconstruction (Sec. 2.2 eq. (9)), error (Sec. 2.4 eq. (13)), min-max ---- */
 
@@ -262,6 +289,11 @@ zm_status zm_cartesian_workspace_size(int n_side, int batch, size_t* bytes);
 zm_status zm_moment_cartesian(const void* d_frames, int n_side, int batch, long long frame_stride, int n, int m,
                               int neumann, double* d_out, void* d_ws, size_t ws_bytes, zm_stream_t stream);
 
+/* Free a plan and its device tables.  ZM_EBUSY (nothing freed) while work
+ * enqueued through the plan (zm_moments, zm_spectra, zm_project,
+ * zm_moments_polar, zm_reconstruct) has not completed on its stream, or
+ * while a batch object built on the plan still exists; synchronise the
+ * stream / destroy the batch and call again. */
 zm_status zm_destroy(zm_plan_t plan);
 
 const char* zm_status_str(zm_status s);

@@ -92,6 +92,8 @@ _SIGS = {
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_sz)]),
     "zm_batch_destroy": (ctypes.c_int, [_vp]),
     "zm_moments_batch": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp]),
+    "zm_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, ctypes.POINTER(_sz)]),
+    "zm_moments_batch_ws": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp, _sz, _vp]),
     "zm_cartesian_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_sz)]),
     "zm_moment_cartesian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _vp, _vp, _sz, _vp]),
@@ -142,9 +144,13 @@ def embed(frames, stream=None):
     B, n, n2 = frames.shape
     if n != n2:
         raise ValueError("embed expects square frames")
+    if frames.dtype not in (torch.float32, torch.float64):
+        raise ValueError(f"embed expects float32 or float64 frames, got {frames.dtype}")
     frames = frames.contiguous()
+    _need(frames, "frames")
     size, _ = pad_size(n)
     out = torch.empty(B, size, size, dtype=frames.dtype, device=frames.device)
+    _keep_alive(stream, out)
     _check(_lib.zm_embed(_vp(frames.data_ptr()), n, B, _vp(out.data_ptr()), int(frames.dtype == torch.float64),
                          _stream_handle(stream)), "zm_embed")
     return out
@@ -169,7 +175,10 @@ def moment_cartesian(frames, n: int, m: int, neumann: bool = False, workspace=No
     _check(_lib.zm_cartesian_workspace_size(N, B, ctypes.byref(need)), "zm_cartesian_workspace_size")
     if workspace is None or workspace.numel() < need.value:
         workspace = torch.empty(max(need.value, 1), dtype=torch.uint8, device=frames.device)
+        _keep_alive(stream, workspace)
+    _need(workspace, "workspace", dtype=torch.uint8, device=frames.device.index)
     out = torch.empty(B, 2, dtype=torch.float64, device=frames.device)
+    _keep_alive(stream, out)
     _check(_lib.zm_moment_cartesian(_vp(frames.data_ptr()), N, B, N * N, int(n), int(m), int(bool(neumann)),
                                     _vp(out.data_ptr()), _vp(workspace.data_ptr()), workspace.numel(),
                                     _stream_handle(stream)), "zm_moment_cartesian")
@@ -186,6 +195,37 @@ def _stream_handle(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _need(t, name, shape=None, dtype=None, min_numel=None, device=None, contiguous=True, on_device=True):
+    """Check a buffer before its pointer crosses the ABI: the kernels trust
+    shape, element type, layout and device, so a mismatch would become an
+    out-of-bounds device access.  Raises ValueError naming the problem."""
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name}: expected dtype {dtype}, got {t.dtype}")
+    if contiguous and not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if min_numel is not None and t.numel() < min_numel:
+        raise ValueError(f"{name}: needs at least {min_numel} elements, has {t.numel()}")
+    if not on_device:
+        return
+    if not t.is_cuda:
+        raise ValueError(f"{name}: must be a CUDA (HIP) tensor")
+    if device is not None and device >= 0 and t.device.index != device:
+        raise ValueError(f"{name}: on device {t.device.index}, the plan is on device {device}")
+
+
+def _keep_alive(stream, *tensors):
+    """Tensors allocated here but used by work on a caller-given stream stay
+    reserved until that stream has passed this point (the caching allocator
+    otherwise hands their memory out again once they are freed)."""
+    if stream is None:
+        return
+    for t in tensors:
+        if t is not None:
+            t.record_stream(stream)
 
 
 class Plan:
@@ -206,10 +246,18 @@ class Plan:
         self.rings, self.angles, self.num_moments = info.rings, info.angles, info.num_moments
         self.rings_padded = info.rings_padded
         self.neumann = bool(info.neumann)
+        self.device = info.device
 
     def close(self):
+        """Free the plan.  Work still in flight on it is waited for first
+        (the library refuses to free a plan that is in use)."""
         if getattr(self, "_h", None):
-            _lib.zm_destroy(self._h)
+            st = _lib.zm_destroy(self._h)
+            if st == ZM_EBUSY and torch.cuda.is_available():
+                torch.cuda.synchronize(self.device if self.device >= 0 else None)
+                st = _lib.zm_destroy(self._h)
+            if st == ZM_EBUSY:
+                raise ZmError(st, "zm_destroy")  # a Batch built on the plan still exists
             self._h = None
 
     def __del__(self):
@@ -250,6 +298,13 @@ class Plan:
         import torch
         return torch.empty(self.workspace_size(batch), dtype=torch.uint8, device=device or "cuda")
 
+    def _check_out(self, out, B):
+        _need(out, "out", shape=(B, self.num_moments, 2), dtype=self._real_dtype(), device=self.device)
+
+    def _check_workspace(self, workspace, B):
+        import torch
+        _need(workspace, "workspace", dtype=torch.uint8, min_numel=self.workspace_size(B), device=self.device)
+
     def moments(self, frames, out=None, workspace=None, stream=None):
         """frames: CUDA tensor [B, H, W] (or [H, W]) of float32 (float64 for
         dtype "f64"), rows contiguous.  Returns [B, num_moments, 2] (re, im)."""
@@ -257,17 +312,16 @@ class Plan:
         squeeze = frames.dim() == 2
         if squeeze:
             frames = frames.unsqueeze(0)
-        if frames.dim() != 3 or frames.shape[1] != self.H or frames.shape[2] != self.W:
-            raise ValueError(f"expected frames of shape [B, {self.H}, {self.W}], got {tuple(frames.shape)}")
-        if frames.dtype != self._real_dtype() or not frames.is_cuda:
-            raise ValueError(f"frames must be a CUDA {self._real_dtype()} tensor")
-        if frames.stride(2) != 1 or frames.stride(1) != self.W:
-            raise ValueError("frame rows must be contiguous")
+        self._check_frames(frames)
         B = frames.shape[0]
         if out is None:
             out = torch.empty(B, self.num_moments, 2, dtype=self._real_dtype(), device=frames.device)
+            _keep_alive(stream, out)
         if workspace is None:
             workspace = self.workspace(B, frames.device)
+            _keep_alive(stream, workspace)
+        self._check_out(out, B)
+        self._check_workspace(workspace, B)
         st = _lib.zm_moments(self._h, _vp(frames.data_ptr()), B, frames.stride(0) if B > 1 else self.H * self.W,
                              _vp(out.data_ptr()), _vp(workspace.data_ptr()), workspace.numel(),
                              _stream_handle(stream))
@@ -277,21 +331,27 @@ class Plan:
     def _check_frames(self, frames):
         if frames.dim() != 3 or frames.shape[1] != self.H or frames.shape[2] != self.W:
             raise ValueError(f"expected frames of shape [B, {self.H}, {self.W}], got {tuple(frames.shape)}")
-        if frames.dtype != self._real_dtype() or not frames.is_cuda:
-            raise ValueError(f"frames must be a CUDA {self._real_dtype()} tensor")
+        if frames.dtype != self._real_dtype():
+            raise ValueError(f"frames must be a CUDA {self._real_dtype()} tensor, got {frames.dtype}")
         if frames.stride(2) != 1 or frames.stride(1) != self.W:
             raise ValueError("frame rows must be contiguous")
+        if frames.shape[0] > 1 and frames.stride(0) < self.H * self.W:
+            raise ValueError("frames must not overlap (frame stride < H * W)")
+        _need(frames, "frames", contiguous=False, device=self.device)
 
     def spectra(self, frames, workspace, stream=None):
         """Stage 1 only: ring spectra of frames [B, H, W] into `workspace`."""
         self._check_frames(frames)
         B = frames.shape[0]
+        self._check_workspace(workspace, B)
         _check(_lib.zm_spectra(self._h, _vp(frames.data_ptr()), B,
                                frames.stride(0) if B > 1 else self.H * self.W, _vp(workspace.data_ptr()),
                                workspace.numel(), _stream_handle(stream)), "zm_spectra")
 
     def project(self, batch, out, workspace, stream=None):
         """Stage 2 only: moments of the spectra left in `workspace` by spectra()."""
+        self._check_out(out, batch)
+        self._check_workspace(workspace, batch)
         _check(_lib.zm_project(self._h, batch, _vp(out.data_ptr()), _vp(workspace.data_ptr()),
                                workspace.numel(), _stream_handle(stream)), "zm_project")
         return out
@@ -305,11 +365,16 @@ class Plan:
         polar = polar.contiguous()
         if polar.shape[1:] != (self.rings, self.angles) or polar.dtype != self._real_dtype():
             raise ValueError("polar must be [B, rings, angles] of the plan's real dtype")
+        _need(polar, "polar", device=self.device)
         B = polar.shape[0]
         if out is None:
             out = torch.empty(B, self.num_moments, 2, dtype=self._real_dtype(), device=polar.device)
+            _keep_alive(stream, out)
         if workspace is None:
             workspace = self.workspace(B, polar.device)
+            _keep_alive(stream, workspace)
+        self._check_out(out, B)
+        self._check_workspace(workspace, B)
         _check(_lib.zm_moments_polar(self._h, _vp(polar.data_ptr()), B, _vp(out.data_ptr()),
                                      _vp(workspace.data_ptr()), workspace.numel(), _stream_handle(stream)),
                "zm_moments_polar")
@@ -331,14 +396,22 @@ def reconstruct(plan, Z, kind="cartesian", one_sided=False, minmax_ref=None, str
     squeeze = Z.dim() == 2
     if squeeze:
         Z = Z.unsqueeze(0)
+    if kind not in ("polar", "cartesian"):
+        raise ValueError(f"kind must be 'polar' or 'cartesian', got {kind!r}")
     Z = Z.contiguous()
     B = Z.shape[0]
+    _need(Z, "Z", shape=(B, plan.num_moments, 2), dtype=plan._real_dtype(), device=plan.device)
     k = RECON_POLAR if kind == "polar" else RECON_CARTESIAN
     shape = (B, plan.rings, plan.angles) if k == RECON_POLAR else (B, plan.H, plan.W)
     out = torch.empty(shape, dtype=plan._real_dtype(), device=Z.device)
     flags = (RECON_ONESIDED if one_sided else 0) | (RECON_MINMAX if minmax_ref is not None else 0)
     ws = _recon_ws(plan, B, Z.device)
-    ref = minmax_ref.contiguous() if minmax_ref is not None else None
+    _keep_alive(stream, out, ws)
+    ref = None
+    if minmax_ref is not None:
+        ref = minmax_ref.unsqueeze(0) if minmax_ref.dim() == 2 else minmax_ref
+        ref = ref.contiguous()
+        _need(ref, "minmax_ref", shape=(B, plan.H, plan.W), dtype=plan._real_dtype(), device=plan.device)
     _check(_lib.zm_reconstruct(plan._h, _vp(Z.data_ptr()), B, _vp(out.data_ptr()), k, flags,
                                _vp(ref.data_ptr()) if ref is not None else None, _vp(ws.data_ptr()), ws.numel(),
                                _stream_handle(stream)), "zm_reconstruct")
@@ -353,7 +426,12 @@ def recon_error(plan, ref, recon, stream=None):
         ref, recon = ref.unsqueeze(0), recon.unsqueeze(0)
     ref, recon = ref.contiguous(), recon.contiguous()
     B = ref.shape[0]
+    for t, name in ((ref, "ref"), (recon, "recon")):
+        _need(t, name, shape=(B, plan.H, plan.W), dtype=plan._real_dtype(), on_device=False)
+    _need(ref, "ref", device=plan.device)
+    _need(recon, "recon", device=plan.device)
     ws = _recon_ws(plan, B, ref.device)
+    _keep_alive(stream, ws)
     out = np.empty((B, 7), dtype=np.float64)
     _check(_lib.zm_recon_error(plan._h, _vp(ref.data_ptr()), _vp(recon.data_ptr()), B,
                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), _vp(ws.data_ptr()), ws.numel(),
@@ -369,10 +447,15 @@ def _jobs(plans, frames, outs):
     n = len(plans)
     if not (len(frames) == n and len(outs) == n):
         raise ValueError("plans, frames and outputs must have the same length")
+    import torch
     arr = (zm_job * n)()
     for i, (p, f, z) in enumerate(zip(plans, frames, outs)):
-        if f.shape[-2:] != (p.H, p.W) or not f.is_contiguous() or z.shape[-2:] != (p.num_moments, 2):
-            raise ValueError(f"job {i}: frame or output shape does not match its plan")
+        # FP64 plans are refused by the library (ZM_EUNSUPPORTED) before any device access
+        real = torch.float64 if p.dtype == "f64" else torch.float32
+        _need(f, f"job {i} frame", shape=(p.H, p.W), dtype=real, on_device=False)
+        _need(z, f"job {i} output", shape=(p.num_moments, 2), dtype=real, on_device=False)
+        _need(f, f"job {i} frame", device=p.device)
+        _need(z, f"job {i} output", device=p.device)
         arr[i].plan = p.handle
         arr[i].d_image = f.data_ptr()
         arr[i].d_Z = z.data_ptr()
@@ -387,7 +470,7 @@ class Batch:
     def __init__(self, plans, frames, outs=None, autotune=False, graph=True):
         import torch
         if outs is None:
-            outs = [torch.empty(p.num_moments, 2, dtype=torch.float32, device=f.device) for p, f in zip(plans, frames)]
+            outs = [torch.empty(p.num_moments, 2, dtype=p._real_dtype(), device=f.device) for p, f in zip(plans, frames)]
         self.plans, self.frames, self.outs = list(plans), list(frames), list(outs)
         jobs = _jobs(self.plans, self.frames, self.outs)
         flags = (BATCH_AUTOTUNE if autotune else 0) | (0 if graph else BATCH_NO_GRAPH)
@@ -427,13 +510,31 @@ class Batch:
             pass
 
 
-def moments_batch(plans, frames, outs=None, stream=None):
-    """One-shot mixed batch (no graph); returns the list of [num_moments, 2] outputs."""
+def batch_workspace_size(plans, frames, outs) -> int:
+    """Device bytes zm_moments_batch_ws needs for these jobs."""
+    jobs = _jobs(plans, frames, outs)
+    n = _sz()
+    _check(_lib.zm_batch_workspace_size(jobs, len(jobs), ctypes.byref(n)), "zm_batch_workspace_size")
+    return n.value
+
+
+def moments_batch(plans, frames, outs=None, workspace=None, stream=None):
+    """One-shot mixed batch (no graph); returns the list of [num_moments, 2]
+    outputs.  With ``workspace`` (a uint8 CUDA tensor of at least
+    batch_workspace_size bytes) the library allocates no device memory."""
     import torch
     if outs is None:
-        outs = [torch.empty(p.num_moments, 2, dtype=torch.float32, device=f.device) for p, f in zip(plans, frames)]
+        outs = [torch.empty(p.num_moments, 2, dtype=p._real_dtype(), device=f.device) for p, f in zip(plans, frames)]
+        _keep_alive(stream, *outs)
     jobs = _jobs(plans, frames, outs)
-    _check(_lib.zm_moments_batch(jobs, len(jobs), _stream_handle(stream)), "zm_moments_batch")
+    if workspace is None:
+        _check(_lib.zm_moments_batch(jobs, len(jobs), _stream_handle(stream)), "zm_moments_batch")
+        return outs
+    n = _sz()
+    _check(_lib.zm_batch_workspace_size(jobs, len(jobs), ctypes.byref(n)), "zm_batch_workspace_size")
+    _need(workspace, "workspace", dtype=torch.uint8, min_numel=n.value, device=plans[0].device)
+    _check(_lib.zm_moments_batch_ws(jobs, len(jobs), _vp(workspace.data_ptr()), workspace.numel(),
+                                    _stream_handle(stream)), "zm_moments_batch_ws")
     return outs
 
 

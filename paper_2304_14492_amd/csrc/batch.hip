@@ -381,18 +381,25 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 struct zm_batch_s {
     int device = 0;
     int njobs = 0, ngroups = 0;
-    std::vector<zm_plan_t> plans;          // per job
-    std::vector<int> job_group, job_slot;  // group and position in the group
+    std::vector<zm_plan_t> plans;           // per job
+    std::vector<int> job_group, job_slot;   // group and position in the group
+    std::vector<std::vector<int>> members;  // jobs of each group
     std::vector<BatchJob> hjobs;
     std::vector<BatchGroup> hgroups;
     std::vector<BatchItem> stage1, stage2;  // natural order
     std::vector<std::vector<void*>> zptrs;  // per group
+    std::vector<BatchItem> hitems;          // queue as uploaded (held until the copy has completed)
+    std::vector<void*> hzptrs;
     int n_items = 0;
     QueueInfo qinfo{};
     int grid = 0;
     int order = 0;  // 0: cost-descending stage 1, 1: natural
-    // device memory
+    // device memory: one block, laid out by batch_layout
+    size_t o_items = 0, o_jobs = 0, o_groups = 0, o_zptr = 0, o_zero = 0;
+    std::vector<size_t> foff;  // spectra of each group
+    std::vector<size_t> zoff;  // first output slot of each group
     char* d_mem = nullptr;
+    bool owns_mem = false;
     size_t d_bytes = 0;
     BatchItem* d_items = nullptr;
     BatchJob* d_jobs = nullptr;
@@ -400,16 +407,20 @@ struct zm_batch_s {
     void** d_zptrs = nullptr;
     unsigned* d_zero = nullptr;  // counters + F16 max slots (cleared before every run)
     int n_zero = 0;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;  // the batch's own stream: uploads, autotuning, capture
+    hipEvent_t done = nullptr;     // completion of the last run
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     unsigned spin_limit = 1u << 24;
+    bool refs_taken = false;       // counted in its plans' batch references
 };
 
 namespace {
 
-zm_status upload(zm_batch_s* b) {
-    std::vector<BatchItem> items;
+// Copies the queue (in the current item order), descriptors and output
+// pointers to the device, asynchronously on `s`; the host copies stay in the
+// batch until the caller has synchronised `s`.
+zm_status upload(zm_batch_s* b, hipStream_t s) {
     std::vector<BatchItem> s1 = b->stage1;
     if (b->order == 0) {
         std::stable_sort(s1.begin(), s1.end(), [&](const BatchItem& x, const BatchItem& y) {
@@ -435,15 +446,24 @@ zm_status upload(zm_batch_s* b) {
     }
     b->qinfo.off[kQueues] = (int)s1.size();
     b->qinfo.len[kQueues] = (int)b->stage2.size();
-    items.insert(items.end(), s1.begin(), s1.end());
-    items.insert(items.end(), b->stage2.begin(), b->stage2.end());
-    b->n_items = (int)items.size();
-    ZM_HIP(hipMemcpy(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice));
-    ZM_HIP(hipMemcpy(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice));
-    ZM_HIP(hipMemcpy(b->d_groups, b->hgroups.data(), b->hgroups.size() * sizeof(BatchGroup), hipMemcpyHostToDevice));
-    std::vector<void*> flat;
-    for (auto& v : b->zptrs) flat.insert(flat.end(), v.begin(), v.end());
-    ZM_HIP(hipMemcpy(b->d_zptrs, flat.data(), flat.size() * sizeof(void*), hipMemcpyHostToDevice));
+    b->hitems.clear();
+    b->hitems.insert(b->hitems.end(), s1.begin(), s1.end());
+    b->hitems.insert(b->hitems.end(), b->stage2.begin(), b->stage2.end());
+    b->n_items = (int)b->hitems.size();
+    b->hzptrs.clear();
+    for (auto& v : b->zptrs) b->hzptrs.insert(b->hzptrs.end(), v.begin(), v.end());
+    ZM_HIP(hipMemcpyAsync(b->d_items, b->hitems.data(), b->hitems.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
+    ZM_HIP(hipMemcpyAsync(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, s));
+    ZM_HIP(hipMemcpyAsync(b->d_groups, b->hgroups.data(), b->hgroups.size() * sizeof(BatchGroup),
+                          hipMemcpyHostToDevice, s));
+    ZM_HIP(hipMemcpyAsync(b->d_zptrs, b->hzptrs.data(), b->hzptrs.size() * sizeof(void*), hipMemcpyHostToDevice, s));
+    return ZM_OK;
+}
+
+zm_status upload_sync(zm_batch_s* b) {
+    zm_status st = upload(b, b->stream);
+    if (st != ZM_OK) return st;
+    ZM_HIP(hipStreamSynchronize(b->stream));
     return ZM_OK;
 }
 
@@ -526,9 +546,12 @@ void tune_cache_store(const std::string& sig, int grid, int order) {
     std::fclose(f);
 }
 
-zm_status check_error_flag(zm_batch_s* b) {
+// Reads the error flag of the last run, which must have completed; the copy
+// runs on `s` and waits for nothing else on the device.
+zm_status check_error_flag(zm_batch_s* b, hipStream_t s) {
     unsigned flag = 0;
-    ZM_HIP(hipMemcpy(&flag, b->d_zero + kCtrGroups + b->ngroups, sizeof(unsigned), hipMemcpyDeviceToHost));
+    ZM_HIP(hipMemcpyAsync(&flag, b->d_zero + kCtrGroups + b->ngroups, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+    ZM_HIP(hipStreamSynchronize(s));
     if (flag) return fail(ZM_EDEVICE, "batch kernel: a projection item waited past its bound");
     return ZM_OK;
 }
@@ -541,7 +564,7 @@ zm_status autotune(zm_batch_s* b, int cus) {
     if (it != g_tune.end()) {
         b->grid = it->second.first;
         b->order = it->second.second;
-        return upload(b);
+        return upload_sync(b);
     }
     hipEvent_t e0, e1;
     ZM_HIP(hipEventCreate(&e0));
@@ -551,7 +574,7 @@ zm_status autotune(zm_batch_s* b, int cus) {
     const int grids[3] = {cus, 2 * cus, 4 * cus};
     for (int order = 0; order < 2; ++order) {
         b->order = order;
-        zm_status st = upload(b);
+        zm_status st = upload_sync(b);
         if (st != ZM_OK) return st;
         for (int gi = 0; gi < 3; ++gi) {
             b->grid = grids[gi];
@@ -575,20 +598,26 @@ zm_status autotune(zm_batch_s* b, int cus) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    zm_status st = check_error_flag(b);
+    zm_status st = check_error_flag(b, b->stream);
     if (st != ZM_OK) return st;
     b->grid = bg;
     b->order = bo;
     tune_cache_store(sig, bg, bo);
-    return upload(b);
+    return upload_sync(b);
+}
+
+void take_refs(zm_batch_s* b, int delta) {
+    for (int g = 0; g < b->ngroups; ++g) zm::add_batch_ref(b->plans[b->members[g][0]], delta);
 }
 
 void destroy_batch(zm_batch_s* b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->done) (void)hipEventDestroy(b->done);
     if (b->stream) (void)hipStreamDestroy(b->stream);
-    if (b->d_mem) (void)hipFree(b->d_mem);
+    if (b->d_mem && b->owns_mem) (void)hipFree(b->d_mem);
+    if (b->refs_taken) take_refs(b, -1);
     delete b;
 }
 
@@ -601,17 +630,10 @@ zm_status fill_pointers(zm_batch_s* b, const zm_job* jobs) {
     return ZM_OK;
 }
 
-}  // namespace
-
-using namespace zm;
-
-extern "C" {
-
-zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out) {
-    if (!jobs || !out || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list and an output pointer");
-    *out = nullptr;
-    if (flags & ~(ZM_BATCH_AUTOTUNE | ZM_BATCH_NO_GRAPH)) return fail(ZM_EINVAL, "unknown batch flags");
-    zm_batch_s* b = new zm_batch_s();
+// Host side of a batch: checks the jobs, groups them by plan, builds the
+// stage-1 and stage-2 items and the descriptors, and lays out the device
+// memory (b->d_bytes); no device call.
+zm_status batch_layout(zm_batch_s* b, const zm_job* jobs, int njobs) {
     b->njobs = njobs;
     b->device = jobs[0].plan ? jobs[0].plan->device : 0;
     if (const char* sl = std::getenv("ZM_BATCH_SPIN_LIMIT")) {
@@ -622,39 +644,29 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         if (end != sl && *end == '\0' && v <= 0xffffffffUL) b->spin_limit = (unsigned)v;
     }
     std::map<zm_plan_t, int> gid;
-    std::vector<std::vector<int>> members;
     for (int i = 0; i < njobs; ++i) {
         zm_plan_t p = jobs[i].plan;
-        if (!p) {
-            destroy_batch(b);
-            return fail(ZM_EINVAL, "job with a null plan");
-        }
-        if (p->device != b->device) {
-            destroy_batch(b);
-            return fail(ZM_EINVAL, "all plans of a batch must be on one device");
-        }
-        if (p->dtype == ZM_F64 || p->n_max > kMaxMomentOrder || !variant_ok(a_index(p->A), a2_index(p->A2))) {
-            destroy_batch(b);
-            return fail(ZM_EUNSUPPORTED,
-                        "batch jobs need an FP32-family dtype, n_max <= 255 and 512 <= angles <= 4096");
-        }
+        if (!p) return fail(ZM_EINVAL, "job with a null plan");
+        if (p->device != b->device) return fail(ZM_EINVAL, "all plans of a batch must be on one device");
+        if (p->dtype == ZM_F64 || p->n_max > zm::kMaxMomentOrder || !variant_ok(a_index(p->A), a2_index(p->A2)))
+            return fail(ZM_EUNSUPPORTED, "batch jobs need an FP32-family dtype, n_max <= 255 and 512 <= angles <= 4096");
         if (!gid.count(p)) {
-            gid[p] = (int)members.size();
-            members.emplace_back();
+            gid[p] = (int)b->members.size();
+            b->members.emplace_back();
         }
         b->plans.push_back(p);
         b->job_group.push_back(gid[p]);
-        b->job_slot.push_back((int)members[gid[p]].size());
-        members[gid[p]].push_back(i);
+        b->job_slot.push_back((int)b->members[gid[p]].size());
+        b->members[gid[p]].push_back(i);
     }
-    b->ngroups = (int)members.size();
-    ZM_DEVICE(b->device);
-    // workspace layout: per group [F of its frames][F16 max slots]; counters
-    std::vector<size_t> foff(b->ngroups);
+    b->ngroups = (int)b->members.size();
+    const auto& members = b->members;
+    // device memory: per group [F of its frames]; queue; descriptors; output pointers; counters
+    b->foff.assign(b->ngroups, 0);
     size_t fbytes = 0;
     for (int g = 0; g < b->ngroups; ++g) {
         const zm_plan_s* p = b->plans[members[g][0]];
-        foff[g] = fbytes;
+        b->foff[g] = fbytes;
         fbytes += align256((size_t)members[g].size() * (size_t)(p->n_max + 1) * 2 * p->Rp * sizeof(float));
     }
     b->n_zero = kCtrGroups + b->ngroups + 1 + njobs;  // heads, group counters, error flag, F16 max per frame
@@ -665,35 +677,25 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         const size_t units = p->items.size() * ((2 * members[g].size() + 31) / 32);
         n_items_max += (units + 7) / 8;
     }
-    const size_t o_items = align256(fbytes);
-    const size_t o_jobs = o_items + align256(n_items_max * sizeof(BatchItem));
-    const size_t o_groups = o_jobs + align256((size_t)njobs * sizeof(BatchJob));
-    const size_t o_zptr = o_groups + align256((size_t)b->ngroups * sizeof(BatchGroup));
-    const size_t o_zero = o_zptr + align256((size_t)njobs * sizeof(void*));
-    b->d_bytes = o_zero + align256((size_t)b->n_zero * sizeof(unsigned));
-    hipError_t e = hipMalloc((void**)&b->d_mem, b->d_bytes);
-    if (e != hipSuccess) {
-        destroy_batch(b);
-        return hip_fail(e, "hipMalloc (batch)");
-    }
-    b->d_items = (BatchItem*)(b->d_mem + o_items);
-    b->d_jobs = (BatchJob*)(b->d_mem + o_jobs);
-    b->d_groups = (BatchGroup*)(b->d_mem + o_groups);
-    b->d_zptrs = (void**)(b->d_mem + o_zptr);
-    b->d_zero = (unsigned*)(b->d_mem + o_zero);
+    b->o_items = align256(fbytes);
+    b->o_jobs = b->o_items + align256(n_items_max * sizeof(BatchItem));
+    b->o_groups = b->o_jobs + align256((size_t)njobs * sizeof(BatchJob));
+    b->o_zptr = b->o_groups + align256((size_t)b->ngroups * sizeof(BatchGroup));
+    b->o_zero = b->o_zptr + align256((size_t)njobs * sizeof(void*));
+    b->d_bytes = b->o_zero + align256((size_t)b->n_zero * sizeof(unsigned));
 
     b->hjobs.resize(njobs);
     b->zptrs.resize(b->ngroups);
+    b->zoff.assign(b->ngroups, 0);
     size_t zbase = 0;
-    std::vector<size_t> zoff(b->ngroups);
     for (int g = 0; g < b->ngroups; ++g) {
         b->zptrs[g].assign(members[g].size(), nullptr);
-        zoff[g] = zbase;
+        b->zoff[g] = zbase;
         zbase += members[g].size();
     }
     for (int i = 0; i < njobs; ++i) {
         const zm_plan_s* p = b->plans[i];
-        const int g = b->job_group[i], k = b->job_slot[i];
+        const int g = b->job_group[i];
         BatchJob& j = b->hjobs[i];
         j.fa.src = nullptr;
         j.fa.src_stride = (long long)p->H * p->W;
@@ -709,9 +711,8 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         j.fa.spx = p->d_spx;
         j.fa.trig = p->d_trig;
         j.fa.tw = (const float*)p->d_tw;
-        j.fa.F = (float*)(b->d_mem + foff[g]) + (size_t)k * (p->n_max + 1) * 2 * p->Rp;
-        // F16 max slots: contiguous per group, after head, counters and flag
-        j.fa.fmaxbuf = p->dtype == ZM_F16X2 ? (float*)(b->d_zero + kCtrGroups + 1 + b->ngroups + zoff[g] + k) : nullptr;
+        j.fa.F = nullptr;
+        j.fa.fmaxbuf = nullptr;
         j.variant = a_index(p->A) * 5 + a2_index(p->A2);
         j.group = g;
         const int tiles = p->Rp / (2 * pairs_of(p->A));
@@ -728,35 +729,91 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         G.pa.thi = p->d_thi;
         G.pa.tlo = p->d_tlo;
         G.pa.rowscale = p->d_rowscale;
-        G.pa.F = b->d_mem + foff[g];
-        G.pa.fmaxbuf = p->dtype == ZM_F16X2 ? (const float*)(b->d_zero + kCtrGroups + 1 + b->ngroups + zoff[g]) : nullptr;
+        G.pa.F = nullptr;
+        G.pa.fmaxbuf = nullptr;
         G.pa.B = n;
         G.pa.M = p->n_max + 1;
         G.pa.Rp = p->Rp;
         G.pa.Mtot = p->num_moments;
         G.pa.Z = nullptr;
-        G.pa.Zptrs = b->d_zptrs + zoff[g];
+        G.pa.Zptrs = nullptr;
         G.dtype = (int)p->dtype;
         G.tiles_total = (unsigned)(n * (p->Rp / (2 * pairs_of(p->A))));
         const int blocks = (G.pa.n_units + 7) / 8;
         for (int k = 0; k < blocks; ++k) b->stage2.push_back(BatchItem{1, g, k, -1});
     }
-    zm_status st = fill_pointers(b, jobs);
+    return fill_pointers(b, jobs);
+}
+
+// Places the batch's device memory at `mem` (d_bytes bytes, 256-byte
+// aligned) and sets the descriptors' pointers into it.
+void batch_bind(zm_batch_s* b, char* mem) {
+    b->d_mem = mem;
+    b->d_items = (BatchItem*)(mem + b->o_items);
+    b->d_jobs = (BatchJob*)(mem + b->o_jobs);
+    b->d_groups = (BatchGroup*)(mem + b->o_groups);
+    b->d_zptrs = (void**)(mem + b->o_zptr);
+    b->d_zero = (unsigned*)(mem + b->o_zero);
+    unsigned* fmax0 = b->d_zero + kCtrGroups + 1 + b->ngroups;  // F16 max slots, contiguous per group
+    for (int i = 0; i < b->njobs; ++i) {
+        const zm_plan_s* p = b->plans[i];
+        const int g = b->job_group[i], k = b->job_slot[i];
+        BatchJob& j = b->hjobs[i];
+        j.fa.F = (float*)(mem + b->foff[g]) + (size_t)k * (p->n_max + 1) * 2 * p->Rp;
+        j.fa.fmaxbuf = p->dtype == ZM_F16X2 ? (float*)(fmax0 + b->zoff[g] + k) : nullptr;
+    }
+    for (int g = 0; g < b->ngroups; ++g) {
+        const zm_plan_s* p = b->plans[b->members[g][0]];
+        BatchGroup& G = b->hgroups[g];
+        G.pa.F = mem + b->foff[g];
+        G.pa.fmaxbuf = p->dtype == ZM_F16X2 ? (const float*)(fmax0 + b->zoff[g]) : nullptr;
+        G.pa.Zptrs = b->d_zptrs + b->zoff[g];
+    }
+}
+
+int device_cus(int device) {
+    hipDeviceProp_t prop;
+    const hipError_t e = hipGetDeviceProperties(&prop, device);
+    return (e == hipSuccess && prop.multiProcessorCount > 0) ? prop.multiProcessorCount : 256;
+}
+
+}  // namespace
+
+using namespace zm;
+
+extern "C" {
+
+zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out) {
+    if (!jobs || !out || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list and an output pointer");
+    *out = nullptr;
+    if (flags & ~(ZM_BATCH_AUTOTUNE | ZM_BATCH_NO_GRAPH)) return fail(ZM_EINVAL, "unknown batch flags");
+    zm_batch_s* b = new zm_batch_s();
+    zm_status st = batch_layout(b, jobs, njobs);
     if (st != ZM_OK) {
         destroy_batch(b);
         return st;
     }
-    hipDeviceProp_t prop;
-    e = hipGetDeviceProperties(&prop, b->device);
-    const int cus = (e == hipSuccess && prop.multiProcessorCount > 0) ? prop.multiProcessorCount : 256;
+    ZM_DEVICE(b->device);
+    char* mem = nullptr;
+    hipError_t e = hipMalloc((void**)&mem, b->d_bytes);
+    if (e != hipSuccess) {
+        destroy_batch(b);
+        return hip_fail(e, "hipMalloc (batch)");
+    }
+    b->owns_mem = true;
+    batch_bind(b, mem);
+    take_refs(b, +1);
+    b->refs_taken = true;
+    const int cus = device_cus(b->device);
     b->grid = 2 * cus;
     b->order = 0;
     e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         destroy_batch(b);
-        return hip_fail(e, "hipStreamCreate");
+        return hip_fail(e, "hipStreamCreate / hipEventCreate");
     }
-    st = upload(b);
+    st = upload_sync(b);
     if (st == ZM_OK && (flags & ZM_BATCH_AUTOTUNE)) st = autotune(b, cus);
     if (st == ZM_OK && !(flags & ZM_BATCH_NO_GRAPH)) st = capture(b);
     if (st != ZM_OK) {
@@ -772,11 +829,13 @@ zm_status zm_batch_update(zm_batch_t b, const zm_job* jobs, int njobs) {
     if (njobs != b->njobs) return fail(ZM_EINVAL, "job count differs from the batch");
     for (int i = 0; i < njobs; ++i)
         if (jobs[i].plan != b->plans[i]) return fail(ZM_EINVAL, "jobs must keep their plans and order");
+    for (int i = 0; i < njobs; ++i)
+        if (!jobs[i].d_image || !jobs[i].d_Z) return fail(ZM_EINVAL, "job with a null frame or output pointer");
+    ZM_DEVICE(b->device);
+    ZM_HIP(hipEventSynchronize(b->done));  // the descriptors may be in use by the last run
     zm_status st = fill_pointers(b, jobs);
     if (st != ZM_OK) return st;
-    ZM_DEVICE(b->device);
-    ZM_HIP(hipDeviceSynchronize());  // descriptors may be in use by a running replay
-    return upload(b);
+    return upload_sync(b);
 }
 
 zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
@@ -785,18 +844,19 @@ zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
     hipStream_t s = (hipStream_t)stream;
     if (b->exec) {
         ZM_HIP(hipGraphLaunch(b->exec, s));
-        return ZM_OK;
+    } else {
+        hipError_t e = enqueue(b, s);
+        if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     }
-    hipError_t e = enqueue(b, s);
-    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+    ZM_HIP(hipEventRecord(b->done, s));
     return ZM_OK;
 }
 
 zm_status zm_batch_check(zm_batch_t b) {
     if (!b) return fail(ZM_EINVAL, "null batch");
     ZM_DEVICE(b->device);
-    ZM_HIP(hipDeviceSynchronize());
-    return check_error_flag(b);
+    ZM_HIP(hipEventSynchronize(b->done));
+    return check_error_flag(b, b->stream);
 }
 
 zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* n_items, size_t* device_bytes) {
@@ -811,7 +871,7 @@ zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* n_items, siz
 zm_status zm_batch_destroy(zm_batch_t b) {
     if (!b) return fail(ZM_EINVAL, "null batch");
     zm::DeviceGuard guard(b->device);
-    (void)hipDeviceSynchronize();
+    if (b->done) (void)hipEventSynchronize(b->done);
     destroy_batch(b);
     return ZM_OK;
 }
@@ -825,7 +885,52 @@ zm_status zm_moments_batch(const zm_job* jobs, int njobs, zm_stream_t stream) {
         hipError_t e = hipStreamSynchronize((hipStream_t)stream);
         if (e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
     }
-    if (st == ZM_OK) st = check_error_flag(b);
+    if (st == ZM_OK) st = check_error_flag(b, (hipStream_t)stream);
+    destroy_batch(b);
+    return st;
+}
+
+zm_status zm_batch_workspace_size(const zm_job* jobs, int njobs, size_t* bytes) {
+    if (!jobs || !bytes || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list and an output pointer");
+    zm_batch_s b;
+    zm_status st = batch_layout(&b, jobs, njobs);
+    if (st != ZM_OK) return st;
+    *bytes = b.d_bytes;
+    return ZM_OK;
+}
+
+zm_status zm_moments_batch_ws(const zm_job* jobs, int njobs, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
+    if (!jobs || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list");
+    if (!d_ws) return fail(ZM_EINVAL, "null workspace");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(ZM_EINVAL, "workspace must be 256-byte aligned");
+    zm_batch_s* b = new zm_batch_s();
+    zm_status st = batch_layout(b, jobs, njobs);
+    if (st == ZM_OK && ws_bytes < b->d_bytes)
+        st = fail(ZM_EINVAL, "workspace too small: need " + std::to_string(b->d_bytes) + " bytes");
+    if (st != ZM_OK) {
+        destroy_batch(b);
+        return st;
+    }
+    zm::DeviceGuard guard(b->device);
+    if (guard.err != hipSuccess) {
+        destroy_batch(b);
+        return hip_fail(guard.err, "hipSetDevice");
+    }
+    batch_bind(b, (char*)d_ws);
+    take_refs(b, +1);
+    b->refs_taken = true;
+    b->grid = 2 * device_cus(b->device);
+    hipStream_t s = (hipStream_t)stream;
+    st = upload(b, s);
+    if (st == ZM_OK) {
+        hipError_t e = enqueue(b, s);
+        if (e != hipSuccess) st = hip_fail(e, "batch kernel launch");
+    }
+    // the host copies of the queue must outlive the uploads, and the error
+    // flag is read after the run: wait for the stream in every case
+    hipError_t e = hipStreamSynchronize(s);
+    if (st == ZM_OK && e != hipSuccess) st = hip_fail(e, "hipStreamSynchronize");
+    if (st == ZM_OK) st = check_error_flag(b, s);
     destroy_batch(b);
     return st;
 }

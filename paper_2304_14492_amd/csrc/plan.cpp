@@ -100,8 +100,38 @@ static void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w
     }
 }
 
+zm_status note_call(zm_plan_s* p, hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ZM_OK;
+    std::lock_guard<std::mutex> lk(p->mu);
+    hipEvent_t ev = nullptr;
+    for (auto& d : p->done)
+        if (d.first == s) ev = d.second;
+    if (!ev) {
+        // take over the slot of a stream whose last call has completed
+        for (auto& d : p->done)
+            if (hipEventQuery(d.second) == hipSuccess) {
+                d.first = s;
+                ev = d.second;
+                break;
+            }
+    }
+    if (!ev) {
+        ZM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        p->done.emplace_back(s, ev);
+    }
+    ZM_HIP(hipEventRecord(ev, s));
+    return ZM_OK;
+}
+
+void add_batch_ref(zm_plan_s* p, int delta) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    p->batch_refs += delta;
+}
+
 static void free_plan(zm_plan_s* p) {
     if (!p) return;
+    for (auto& d : p->done) (void)hipEventDestroy(d.second);
     void* bufs[] = {p->d_spx, p->d_trig, p->d_tw, p->d_table, p->d_jac, p->d_thi,
                     p->d_tlo, p->d_rowscale, p->d_items, p->d_rowmap};
     for (void* b : bufs)
@@ -480,14 +510,7 @@ static zm_status run_spectra(zm_plan_t p, const void* src, int batch, long long 
     return ZM_OK;
 }
 
-zm_status zm_spectra(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_ws,
-                     size_t ws_bytes, zm_stream_t stream) {
-    if (p && batch > 1 && image_stride < (long long)p->H * p->W)
-        return fail(ZM_EINVAL, "image_stride must be >= H * W");
-    return run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0);
-}
-
-zm_status zm_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
+static zm_status run_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
     zm_status st = check_run(p, batch, d_ws, ws_bytes);
     if (st != ZM_OK || batch == 0) return st;
     if (!d_Z) return fail(ZM_EINVAL, "null output pointer");
@@ -497,12 +520,32 @@ zm_status zm_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_by
     return ZM_OK;
 }
 
+// Marks the completion of the call's work on the plan (for zm_destroy).
+static zm_status noted(zm_status st, zm_plan_t p, int batch, zm_stream_t stream) {
+    if (st != ZM_OK || batch <= 0) return st;
+    ZM_DEVICE(p->device);
+    return note_call(p, (hipStream_t)stream);
+}
+
+zm_status zm_spectra(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_ws,
+                     size_t ws_bytes, zm_stream_t stream) {
+    if (p && batch > 1 && image_stride < (long long)p->H * p->W)
+        return fail(ZM_EINVAL, "image_stride must be >= H * W");
+    return noted(run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0), p, batch, stream);
+}
+
+zm_status zm_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
+    return noted(run_project(p, batch, d_Z, d_ws, ws_bytes, stream), p, batch, stream);
+}
+
 zm_status zm_moments(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_Z, void* d_ws,
                      size_t ws_bytes, zm_stream_t stream) {
     if (batch > 0 && !d_Z) return fail(ZM_EINVAL, "null output pointer");
-    zm_status st = zm_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream);
-    if (st != ZM_OK) return st;
-    return zm_project(p, batch, d_Z, d_ws, ws_bytes, stream);
+    if (p && batch > 1 && image_stride < (long long)p->H * p->W)
+        return fail(ZM_EINVAL, "image_stride must be >= H * W");
+    zm_status st = run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0);
+    if (st == ZM_OK) st = run_project(p, batch, d_Z, d_ws, ws_bytes, stream);
+    return noted(st, p, batch, stream);
 }
 
 zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_Z, void* d_ws, size_t ws_bytes,
@@ -510,8 +553,8 @@ zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_
     if (!p) return fail(ZM_EINVAL, "null plan");
     if (batch > 0 && !d_Z) return fail(ZM_EINVAL, "null output pointer");
     zm_status st = run_spectra(p, d_polar, batch, (long long)p->R * p->A, d_ws, ws_bytes, stream, 1);
-    if (st != ZM_OK) return st;
-    return zm_project(p, batch, d_Z, d_ws, ws_bytes, stream);
+    if (st == ZM_OK) st = run_project(p, batch, d_Z, d_ws, ws_bytes, stream);
+    return noted(st, p, batch, stream);
 }
 
 zm_status zm_recon_workspace_size(zm_plan_t p, int batch, size_t* bytes) {
@@ -551,7 +594,7 @@ zm_status zm_reconstruct(zm_plan_t p, const void* d_Z, int batch, void* d_out, i
         e = launch_minmax(p, d_ref, d_out, batch, part, mm, s);
         if (e != hipSuccess) return hip_fail(e, "min-max kernel launch");
     }
-    return ZM_OK;
+    return note_call(p, s);
 }
 
 zm_status zm_recon_error(zm_plan_t p, const void* d_ref, const void* d_recon, int batch, double* host_out,
@@ -607,6 +650,13 @@ zm_status zm_embed(const void* d_src, int n, int batch, void* d_dst, int is_doub
 zm_status zm_destroy(zm_plan_t p) {
     if (!p) return fail(ZM_EINVAL, "null plan");
     zm::DeviceGuard guard(p->device);  // frees on the plan's device even if selecting it failed
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (p->batch_refs > 0) return fail(ZM_EBUSY, "a batch built on this plan still exists; destroy it first");
+        for (auto& d : p->done)
+            if (hipEventQuery(d.second) == hipErrorNotReady)
+                return fail(ZM_EBUSY, "work enqueued on this plan has not completed; synchronise its stream first");
+    }
     free_plan(p);
     return ZM_OK;
 }

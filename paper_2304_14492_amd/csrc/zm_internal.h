@@ -5,7 +5,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <mutex>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "zm.h"
@@ -113,9 +115,22 @@ struct zm_plan_s {
     zm_item* d_items = nullptr;
     int* d_rowmap = nullptr;             // operand row -> canonical idx (-1 for padding)
     size_t resident = 0;
+
+    // What zm_destroy checks before freeing (guarded by mu): the completion
+    // event of the last call enqueued on each stream, and the number of
+    // batch objects built on the plan.
+    std::mutex mu;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> done;
+    int batch_refs = 0;
 };
 
 namespace zm {
+// Records on `s` the completion of the work just enqueued on plan p (not
+// while `s` is being captured into a graph).
+zm_status note_call(zm_plan_s* p, hipStream_t s);
+// Adds `delta` to the plan's count of batch objects built on it.
+void add_batch_ref(zm_plan_s* p, int delta);
+
 // Kernels launchers (each returns hipSuccess or the launch error).
 hipError_t launch_zrp_table(const zm_plan_s* p, const double* d_rho, const double* d_ck, hipStream_t s);
 hipError_t launch_fold(const zm_plan_s* p, const double* d_w, hipStream_t s);

@@ -88,7 +88,7 @@ def find_duplicates(frames, orders=(16, 20), rtol: float = 1e-5, dtype: str = "f
     if plan is None:
         plan = Plan(nmax, H, W, dtype=dtype)
     ws = plan.workspace(min(chunk, K))
-    Z = torch.empty(K, plan.num_moments, 2, dtype=torch.float32, device=frames.device)
+    Z = torch.empty(K, plan.num_moments, 2, dtype=plan._real_dtype(), device=frames.device)
     for s in range(0, K, chunk):
         e = min(K, s + chunk)
         plan.moments(frames[s:e].contiguous(), out=Z[s:e], workspace=ws, stream=stream)

@@ -159,3 +159,56 @@ def test_batch_rejects_unsupported(zm):
     p2 = zm.Plan(10, 64, 64, dtype="f32")  # angles 256 < 512
     with pytest.raises(zm.ZmError):
         zm.moments_batch([p2], [torch.zeros(64, 64, device="cuda")])
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16x2"])
+def test_caller_workspace_batch_bit_exact(zm, dtype):
+    # zm_moments_batch_ws: the same batch in caller-owned device memory, twice
+    # in a row in one workspace (the second with fewer jobs), on a side stream
+    specs = [(256, 30, 11), (512, 100, 12), (256, 30, 13), (384, 50, 14), (1024, 50, 15)]
+    frames = _frames(specs)
+    plans = _plans(zm, specs, dtype)
+    outs = [torch.empty(p.num_moments, 2, device="cuda") for p in plans]
+    need = zm.batch_workspace_size(plans, frames, outs)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ValueError):
+        zm.moments_batch(plans, frames, outs, workspace=ws[:need - 1])
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        zm.moments_batch(plans, frames, outs, workspace=ws, stream=s)
+        k = 3
+        outs2 = [torch.full((p.num_moments, 2), float("nan"), device="cuda") for p in plans[:k]]
+        zm.moments_batch(plans[:k], frames[:k], outs2, workspace=ws, stream=s)
+    torch.cuda.synchronize()
+    ref = [p.moments(f) for p, f in zip(plans, frames)]
+    torch.cuda.synchronize()
+    for z, r in zip(outs, ref):
+        assert torch.equal(z, r)
+    for z, r in zip(outs2, ref[:k]):
+        assert torch.equal(z, r)
+
+
+def test_destroy_reports_busy(zm):
+    # a plan with work in flight, or with a batch built on it, is not freed
+    plan = zm.Plan(100, 1024, 1024, dtype="f32")
+    x = torch.rand(4, 1024, 1024, device="cuda")
+    out = torch.empty(4, plan.num_moments, 2, device="cuda")
+    ws = plan.workspace(4)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        torch.cuda._sleep(200_000_000)  # keeps the stream busy for tens of milliseconds
+        plan.moments(x, out=out, workspace=ws, stream=s)
+    assert zm._lib.zm_destroy(plan.handle) == zm.ZM_EBUSY
+    s.synchronize()
+    b = zm.Batch([plan], [x[0]], graph=False)
+    assert zm._lib.zm_destroy(plan.handle) == zm.ZM_EBUSY
+    b.run()
+    b.check()
+    b.close()
+    ref = plan.moments(x[:1])
+    torch.cuda.synchronize()
+    assert torch.equal(b.outs[0], ref[0])
+    plan.close()
+    assert plan.handle is None
