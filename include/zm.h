@@ -165,6 +165,23 @@ zm_status zm_spectra(zm_plan_t plan, const void* d_images, int batch, long long 
                      size_t ws_bytes, zm_stream_t stream);
 zm_status zm_project(zm_plan_t plan, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream);
 
+/* zm_moments without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation): the spectra workspace is a static device array of
+ * zm_static_scratch_bytes() bytes (32 MiB) that the library holds on every
+ * device it runs on until the process ends.  Same arguments, layout and
+ * results as zm_moments (bit-identical).  The call allocates nothing: no
+ * hipMalloc / hipFree, no event creation (the completion event zm_destroy
+ * checks is one made with the plan, reused when its last use has finished).
+ * ZM_EINVAL if the batch needs more scratch than the array holds (the error
+ * text gives the largest batch of this plan that fits: 19 frames of 4K at
+ * n_max 200).  All calls on one device share the array, which keeps the
+ * last call's contents: calls that overlap on one device (several streams
+ * or threads) race and must be serialised by the caller. */
+zm_status zm_moments_static(zm_plan_t plan, const void* d_images, int batch, long long image_stride, void* d_Z,
+                            zm_stream_t stream);
+size_t zm_static_scratch_bytes(void);
+
 /* Moments from a polar image already on the grid (bypasses the resampler):
  * d_polar is [batch][R][A] (float, or double for ZM_F64). */
 zm_status zm_moments_polar(zm_plan_t plan, const void* d_polar, int batch, void* d_Z, void* d_ws,

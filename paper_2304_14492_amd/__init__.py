@@ -77,6 +77,8 @@ _SIGS = {
     "zm_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_sz)]),
     "zm_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp, _sz, _vp]),
     "zm_moments_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "zm_moments_static": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp]),
+    "zm_static_scratch_bytes": (_sz, []),
     "zm_spectra": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _sz, _vp]),
     "zm_project": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "zm_reconstruct": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _sz, _vp]),
@@ -326,6 +328,26 @@ class Plan:
                              _vp(out.data_ptr()), _vp(workspace.data_ptr()), workspace.numel(),
                              _stream_handle(stream))
         _check(st, "zm_moments")
+        return out[0] if squeeze else out
+
+    def moments_static(self, frames, out=None, stream=None):
+        """zm_moments_static: as moments(), with the library's static device
+        scratch as the workspace (no allocation in the library; calls that
+        overlap on one device race).  ``out`` must be given by callers that
+        cannot allocate."""
+        import torch
+        squeeze = frames.dim() == 2
+        if squeeze:
+            frames = frames.unsqueeze(0)
+        self._check_frames(frames)
+        B = frames.shape[0]
+        if out is None:
+            out = torch.empty(B, self.num_moments, 2, dtype=self._real_dtype(), device=frames.device)
+            _keep_alive(stream, out)
+        self._check_out(out, B)
+        _check(_lib.zm_moments_static(self._h, _vp(frames.data_ptr()), B,
+                                      frames.stride(0) if B > 1 else self.H * self.W, _vp(out.data_ptr()),
+                                      _stream_handle(stream)), "zm_moments_static")
         return out[0] if squeeze else out
 
     def _check_frames(self, frames):

@@ -100,7 +100,7 @@ static void gauss_legendre(int N, std::vector<double>& x, std::vector<double>& w
     }
 }
 
-zm_status note_call(zm_plan_s* p, hipStream_t s) {
+zm_status note_call(zm_plan_s* p, hipStream_t s, bool may_create) {
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone) return ZM_OK;
     std::lock_guard<std::mutex> lk(p->mu);
@@ -117,10 +117,43 @@ zm_status note_call(zm_plan_s* p, hipStream_t s) {
             }
     }
     if (!ev) {
+        if (!may_create) return ZM_OK;
         ZM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         p->done.emplace_back(s, ev);
     }
     ZM_HIP(hipEventRecord(ev, s));
+    return ZM_OK;
+}
+
+// ---- Static scratch for zm_moments_static (callers that cannot allocate) ----
+// The spectra workspace of zm_moments_static lives in this array; every
+// device the library runs on holds its own copy until the process ends.  Its
+// device address is looked up once per device (with that device current)
+// when the first plan on the device is created; host code uses only that
+// address, never the array's name (a host-side stand-in).
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+}  // namespace zm
+
+static __device__ __align__(256) char scratch[zm::kStaticScratchBytes];
+
+namespace zm {
+
+// Device address of `scratch` on `device`, which must be the current device.
+static zm_status scratch_address(int device, void** out) {
+    if (device < 0 || device >= kMaxScratchDevices)
+        return fail(ZM_EUNSUPPORTED, "static scratch: device ordinal beyond the supported range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
     return ZM_OK;
 }
 
@@ -319,10 +352,10 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
         if (e_ != hipSuccess) ZM_TRY(hip_fail(e_, #call)); \
     } while (0)
 
-    size_t scratch = 0;
-    ZM_TRY(dev_alloc(&d_rho, R, &scratch));
-    ZM_TRY(dev_alloc(&d_w, R, &scratch));
-    ZM_TRY(dev_alloc(&d_ck, p->NK, &scratch));
+    size_t tmp_bytes = 0;
+    ZM_TRY(dev_alloc(&d_rho, R, &tmp_bytes));
+    ZM_TRY(dev_alloc(&d_w, R, &tmp_bytes));
+    ZM_TRY(dev_alloc(&d_ck, p->NK, &tmp_bytes));
     ZM_TRY(dev_alloc(&p->d_spx, R, &total));
     ZM_TRY(dev_alloc(&p->d_trig, 2 * (size_t)A, &total));
     ZM_TRY(dev_alloc(&p->d_table, (size_t)p->num_moments * R, &total));
@@ -410,6 +443,15 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
         }
         e = hipStreamSynchronize(nullptr);
         if (e != hipSuccess) ZM_TRY(hip_fail(e, "plan construction"));
+    }
+    {
+        // one completion event made up front (reused by calls that must not
+        // allocate), and the static scratch's address on this device
+        hipEvent_t ev = nullptr;
+        ZM_TRYHIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        p->done.emplace_back(nullptr, ev);
+        void* sp = nullptr;
+        ZM_TRY(scratch_address(p->device, &sp));
     }
 #undef ZM_TRY
 #undef ZM_TRYHIP
@@ -555,6 +597,33 @@ zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_
     zm_status st = run_spectra(p, d_polar, batch, (long long)p->R * p->A, d_ws, ws_bytes, stream, 1);
     if (st == ZM_OK) st = run_project(p, batch, d_Z, d_ws, ws_bytes, stream);
     return noted(st, p, batch, stream);
+}
+
+size_t zm_static_scratch_bytes(void) { return kStaticScratchBytes; }
+
+zm_status zm_moments_static(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_Z,
+                            zm_stream_t stream) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch < 0) return fail(ZM_EINVAL, "negative batch");
+    if (batch == 0) return ZM_OK;
+    if (!d_Z) return fail(ZM_EINVAL, "null output pointer");
+    if (batch > 1 && image_stride < (long long)p->H * p->W) return fail(ZM_EINVAL, "image_stride must be >= H * W");
+    const size_t need = workspace_bytes(p, batch);
+    if (need > kStaticScratchBytes) {
+        size_t fit = 0;
+        while (fit < 65535 && workspace_bytes(p, (int)fit + 1) <= kStaticScratchBytes) ++fit;
+        return fail(ZM_EINVAL, "batch needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                   std::to_string(kStaticScratchBytes) + " bytes (at most " + std::to_string(fit) +
+                                   " frames of this plan per call)");
+    }
+    ZM_DEVICE(p->device);
+    void* ws = nullptr;
+    zm_status st = scratch_address(p->device, &ws);
+    if (st != ZM_OK) return st;
+    st = run_spectra(p, d_images, batch, image_stride, ws, kStaticScratchBytes, stream, 0);
+    if (st == ZM_OK) st = run_project(p, batch, d_Z, ws, kStaticScratchBytes, stream);
+    if (st != ZM_OK) return st;
+    return note_call(p, (hipStream_t)stream, false);
 }
 
 zm_status zm_recon_workspace_size(zm_plan_t p, int batch, size_t* bytes) {

@@ -126,8 +126,10 @@ struct zm_plan_s {
 
 namespace zm {
 // Records on `s` the completion of the work just enqueued on plan p (not
-// while `s` is being captured into a graph).
-zm_status note_call(zm_plan_s* p, hipStream_t s);
+// while `s` is being captured into a graph).  Without may_create it only
+// reuses one of the plan's events (one is made with the plan), so the call
+// allocates nothing; if every event is still pending it records nothing.
+zm_status note_call(zm_plan_s* p, hipStream_t s, bool may_create = true);
 // Adds `delta` to the plan's count of batch objects built on it.
 void add_batch_ref(zm_plan_s* p, int delta);
 

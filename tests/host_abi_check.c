@@ -37,6 +37,7 @@ static void check_null_arguments(void) {
     CHECK(zm_ring_nodes(NULL, NULL, NULL, 0) == ZM_EINVAL);
     CHECK(zm_workspace_size(NULL, 1, &bytes) == ZM_EINVAL);
     CHECK(zm_moments(NULL, NULL, 1, 0, NULL, NULL, 0, NULL) == ZM_EINVAL);
+    CHECK(zm_moments_static(NULL, NULL, 1, 0, NULL, NULL) == ZM_EINVAL);
     CHECK(zm_spectra(NULL, NULL, 1, 0, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_project(NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_moments_polar(NULL, NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);
@@ -101,6 +102,7 @@ int main(void) {
     CHECK(zm_num_moments(-1) == -1);
     CHECK(zm_index(3, 2) == -1 && zm_index(2, 3) == -1 && zm_index(-1, 0) == -1 && zm_index(4, -2) == -1);
     for (int s = 0; s >= -5; --s) CHECK(strncmp(zm_status_str((zm_status)s), "ZM_", 3) == 0);
+    CHECK(zm_static_scratch_bytes() == ((size_t)32 << 20));
     check_null_arguments();
     pthread_t th[8];
     for (long i = 0; i < 8; ++i) pthread_create(&th[i], NULL, worker, (void*)i);
