@@ -14,10 +14,15 @@ value, unit, ms_per_step, config, ...):
                  traffic = HBM bytes per launch from the committed rocprofv3
                  counter summary (null once the kernel source has changed)
   projection     the projection kernel's useful FLOP rate vs the MFMA peak
-  split_bf16     the same step with the hi/lo split-BF16 projection
-  cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s
+  split_bf16, split_f16
+                 the same step with the hi/lo split-BF16 / split-FP16
+                 projection: the spectra kernel's HBM rate, the projection's
+                 useful and issued MFMA fractions and its operand HBM rate
+  cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s,
+                 on all host threads and (single_thread) on one
   batch_form     64 mixed square frames (sides 256..2048, N_max 30/50/100) in
-                 one persistent launch replayed from a HIP graph; beside it the
+                 one persistent launch replayed from a HIP graph, with its HBM
+                 rate (algorithmic bytes of the whole batch); beside it the
                  same frames as per-plan zm_moments launches
   latency        the serving form: Poisson arrivals at a fixed rate of
                  640x480 / 1080p / 4K frames (N_max 30/100/200) from pinned host
@@ -104,6 +109,33 @@ def projection_flops_per_frame():
     return 4 * RINGS * ((NMAX // 2 + 1) ** 2)
 
 
+def operand_bytes(plan):
+    """Bytes of a plan's projection operand (rows padded to 16 per m block,
+    rings to rings_padded; FP32, or two 16-bit parts for the splits)."""
+    rows = sum((plan.n_max - m) // 2 // 16 * 16 + 16 for m in range(plan.n_max + 1))
+    return rows * plan.rings_padded * 4
+
+
+def projection_entry(dtype, proj_ms, batch):
+    """Projection figures for one dtype: useful and issued MFMA rates (the
+    split forms issue three products per useful one) against the dtype's
+    dense peak, and the HBM rate of its operands (operand table once, spectra
+    read, moments written) against 8 TB/s."""
+    import paper_2304_14492_amd as zm
+    plan = zm.Plan.__new__(zm.Plan)
+    plan.n_max, plan.rings_padded = NMAX, (RINGS + 31) // 32 * 32
+    flops = projection_flops_per_frame() * batch
+    issued = flops * (1 if dtype == "f32" else 3)
+    tf = flops / (proj_ms / 1e3) / 1e12
+    nbytes = operand_bytes(plan) + batch * ((NMAX + 1) * 2 * RINGS * 4 + (NMAX // 2 + 1) ** 2 * 2 * 4)
+    gbs = nbytes / (proj_ms / 1e3) / 1e9
+    return {"kernel": "project_kernel", "avg_launch_ms": round(proj_ms, 4), "useful_tflops": round(tf, 2),
+            "peak_tflops": MFMA_PEAK_TFLOPS[dtype], "frac": round(tf / MFMA_PEAK_TFLOPS[dtype], 4),
+            "issued_frac": round(issued / (proj_ms / 1e3) / 1e12 / MFMA_PEAK_TFLOPS[dtype], 4),
+            "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes}}
+
+
 def make_frames(batch):
     import synth
     from synth.frames import FrameSpec
@@ -180,6 +212,22 @@ def cpu_baseline(budget_s):
                        "exact radial table built once beforehand (plan-time, untimed)")
 
 
+def cpu_baseline_single_thread(budget_s):
+    """The same oracle timing on one host thread, in a child process started
+    with OMP_NUM_THREADS=1 (the oracle's OpenMP team is fixed at load)."""
+    import subprocess
+    code = ("import json, bench; r = bench.cpu_baseline(%r); print('CPU1 ' + json.dumps(r))" % budget_s)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                         timeout=600)
+    for line in out.stdout.splitlines():
+        if line.startswith("CPU1 "):
+            r = json.loads(line[5:])
+            r["cores"] = 1
+            return r
+    raise RuntimeError("single-thread oracle run failed: " + out.stderr[-2000:])
+
+
 def batch_form(steps):
     import torch
     import paper_2304_14492_amd as zm
@@ -223,9 +271,22 @@ def batch_form(steps):
     e1.record()
     torch.cuda.synchronize()
     ms_plan = e0.elapsed_time(e1) / steps
+    # algorithmic HBM bytes of one batch: every frame's disk footprint read
+    # once, its ring spectra written and read back once, its moments written,
+    # and each plan's projection operand read once
+    nbytes = 0
+    for (side, nmax, _), pl in zip(specs, plans):
+        spec_b = (nmax + 1) * 2 * pl.rings * 4
+        nbytes += 4 * disk_pixels(side, side) + 2 * spec_b + pl.num_moments * 2 * 4
+    for pl in cache.values():
+        nbytes += operand_bytes(pl)
+    gbs = nbytes / (ms / 1e3) / 1e9
     return {"images_per_s": round(len(frames) / (ms / 1e3), 1), "ms_per_batch": round(ms, 4), "frames": len(frames),
             "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "queue_items": cfg["n_items"],
-            "per_plan_launches_ms": round(ms_plan, 4)}
+            "per_plan_launches_ms": round(ms_plan, 4),
+            "roofline": {"bound": "hbm", "kernel": "batch_kernel (persistent: resample + FFT + projection)",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes}}
 
 
 def reconstruction(reps=3):
@@ -434,19 +495,26 @@ def main():
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.batch),
                      "bytes_per_launch": bytes_launch, "avg_launch_ms": round(r["spec_ms"], 4)},
-        "projection": {"kernel": "project_kernel", "avg_launch_ms": round(r["proj_ms"], 4),
-                       "useful_tflops": round(proj_tflops, 2), "peak_tflops": MFMA_PEAK_TFLOPS[args.dtype],
-                       "frac": round(proj_tflops / MFMA_PEAK_TFLOPS[args.dtype], 4)},
+        "projection": projection_entry(args.dtype, r["proj_ms"], args.batch),
     }
+    assert abs(res["projection"]["useful_tflops"] - proj_tflops) < 0.01 * proj_tflops + 0.01
     if not args.no_split and args.dtype == "f32":
         del r
-        torch.cuda.empty_cache()
-        r2 = run_gpu(args.batch, args.steps, args.warmup, "bf16x2")
-        ms2 = r2["total_ms"] / args.steps
-        res["split_bf16"] = {"value": round(args.batch / (ms2 / 1e3), 2), "unit": "images/s",
-                             "ms_per_step": round(ms2, 4), "projection_ms": round(r2["proj_ms"], 4),
-                             "projection_useful_tflops": round(flops_launch / (r2["proj_ms"] / 1e3) / 1e12, 2)}
-        print(f"[bench] bf16x2: {ms2:.3f} ms/step, projection {r2['proj_ms']:.3f} ms", file=sys.stderr, flush=True)
+        for dt, key in (("bf16x2", "split_bf16"), ("f16x2", "split_f16")):
+            torch.cuda.empty_cache()
+            r2 = run_gpu(args.batch, args.steps, args.warmup, dt)
+            ms2 = r2["total_ms"] / args.steps
+            sb = bytes_launch / (r2["spec_ms"] / 1e3) / 1e9
+            res[key] = {"value": round(args.batch / (ms2 / 1e3), 2), "unit": "images/s",
+                        "ms_per_step": round(ms2, 4),
+                        "spectra_roofline": {"bound": "hbm", "kernel": "polar_fft_kernel",
+                                             "achieved": round(sb, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                             "frac": round(sb / HBM_PEAK_GBS, 4),
+                                             "avg_launch_ms": round(r2["spec_ms"], 4)},
+                        "projection": projection_entry(dt, r2["proj_ms"], args.batch)}
+            print(f"[bench] {dt}: {ms2:.3f} ms/step, projection {r2['proj_ms']:.3f} ms", file=sys.stderr,
+                  flush=True)
+            del r2
     if not args.no_batch_form:
         torch.cuda.empty_cache()
         res["batch_form"] = batch_form(args.steps)
@@ -472,6 +540,7 @@ def main():
     if args.cpu_seconds > 0:
         print("[bench] timing the CPU oracle ...", file=sys.stderr, flush=True)
         res["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+        res["cpu_baseline"]["single_thread"] = cpu_baseline_single_thread(args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 
