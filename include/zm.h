@@ -124,6 +124,15 @@ zm_status zm_plan_info(zm_plan_t plan, zm_plan_info_t* out);
  * least num_moments * R.  Synchronous. */
 zm_status zm_radial_table(zm_plan_t plan, double* host_out, size_t n_elems);
 
+/* Copy the projection operand the plan holds on the device to host memory,
+ * decoded to FP64 in the layout of zm_radial_table: host_out[idx * R + r] =
+ * the folded value 2(n+1)/(A eps_m) w_r R_nm(rho_r) as the projection sees it
+ * (FP64, FP32, hi + lo bfloat16, or (hi + lo half) times the row's scale).
+ * For checks of the precision forms against the FP64 table of eq. (7)
+ * (Sec. 2.1; the stability study of Sec. 3.1).  ZM_EUNSUPPORTED for plans
+ * without an operand (n_max > 255).  Synchronous. */
+zm_status zm_operand_table(zm_plan_t plan, double* host_out, size_t n_elems);
+
 /* Copy the plan's ring nodes rho_r and weights w_r (FP64, R each) to host. */
 zm_status zm_ring_nodes(zm_plan_t plan, double* rho_out, double* w_out, size_t n_elems);
 

@@ -74,6 +74,7 @@ _SIGS = {
     "zm_plan_info": (ctypes.c_int, [_vp, ctypes.POINTER(zm_plan_info_t)]),
     "zm_radial_table": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _sz]),
     "zm_ring_nodes": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double), _sz]),
+    "zm_operand_table": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_double), _sz]),
     "zm_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_sz)]),
     "zm_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp, _sz, _vp]),
     "zm_moments_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),

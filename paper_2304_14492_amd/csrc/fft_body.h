@@ -134,6 +134,15 @@ struct RealTraits<double> {
     static constexpr int kMaxA2 = 128;  // LDS bound of the FP64 variant
 };
 
+// Bilinear interpolation of the taps (v00, v01) of row i0 and (v10, v11) of
+// row i0 + 1 at fractions (fx, fy); every gather path uses this expression.
+template <typename Real>
+__device__ __forceinline__ Real bilerp(Real v00, Real v01, Real v10, Real v11, Real fx, Real fy) {
+    const Real top = v00 + fx * (v01 - v00);
+    const Real bot = v10 + fx * (v11 - v10);
+    return top + fy * (bot - top);
+}
+
 // Bilinear sample of the frame from tap origin (j0, i0) and fractions
 // (fx, fy) in [0, 1].  CHECK selects the path that treats taps outside the
 // frame as 0 (tap indices are clamped before the loads, so no load leaves the
@@ -162,9 +171,7 @@ __device__ __forceinline__ Real bilinear_idx(const Real* __restrict__ img, int H
         v10 = r1p[0];
         v11 = r1p[1];
     }
-    const Real top = v00 + fx * (v01 - v00);
-    const Real bot = v10 + fx * (v11 - v10);
-    return top + fy * (bot - top);
+    return bilerp(v00, v01, v10, v11, fx, fy);
 }
 
 // floor and fraction of a pixel coordinate
@@ -174,7 +181,7 @@ struct Coord {
     Real f;
 };
 template <typename Real>
-__device__ __forceinline__ Coord<Real> split_coord(double v) {
+__host__ __device__ __forceinline__ Coord<Real> split_coord(double v) {
     const double fl = floor(v);
     return Coord<Real>{(int)fl, (Real)(v - fl)};
 }
@@ -182,8 +189,39 @@ __device__ __forceinline__ Coord<Real> split_coord(double v) {
 // fraction 1 - frac(v) (a fraction of exactly 1 when v is an integer, which
 // bilinear interpolation treats identically to fraction 0 one tap further).
 template <typename Real>
-__device__ __forceinline__ Coord<Real> mirror_coord(Coord<Real> c, int K) {
+__host__ __device__ __forceinline__ Coord<Real> mirror_coord(Coord<Real> c, int K) {
     return Coord<Real>{K - c.i - 1, (Real)1 - c.f};
+}
+
+// (cos, sin) of the base angle 2 pi b / A, b < A / 4: the table pair of
+// b mod (A / 32) rotated by the table pair of (A / 32) floor(b / (A / 32)),
+// one rounded product each (written with explicit FMAs, so every gather
+// path, and the host's window planning, forms the same bits).
+__host__ __device__ __forceinline__ void rotate_pair(double c0, double s0, double ci, double si, double& c, double& s) {
+    c = fma(c0, ci, -(s0 * si));
+    s = fma(s0, ci, c0 * si);
+}
+
+// Tap origin (row i, column j) and fractions of the sample at radius sr
+// (pixels) and angle b + u A / 4, with (cb, sb) the pair of base angle b:
+// x = cx + sr (cb, -sb, -cb, sb)[u], y = cy - sr (sb, cb, -sb, -cb)[u].
+// The negated offsets are mirrors of cx + sr c and cy + sr s (2 cx = W - 1,
+// 2 cy = H - 1), so the four quarter turns of one base angle sit exactly on
+// rotated pixel positions.
+template <typename Real>
+struct TapPos {
+    Coord<Real> x, y;
+};
+template <typename Real>
+__host__ __device__ __forceinline__ TapPos<Real> sample_pos(double cx, double cy, int W, int H, double sr, double cb,
+                                                            double sb, int u) {
+    const double c1 = (u & 1) ? sb : cb;
+    const double c2 = (u & 1) ? cb : sb;
+    Coord<Real> X = split_coord<Real>(fma(sr, c1, cx));
+    Coord<Real> Y = split_coord<Real>(fma(sr, c2, cy));
+    if (u == 1 || u == 2) X = mirror_coord(X, W - 1);
+    if (u == 0 || u == 1) Y = mirror_coord(Y, H - 1);
+    return TapPos<Real>{X, Y};
 }
 
 template <typename Real>
@@ -252,6 +290,109 @@ struct FftLds {
     static constexpr size_t cplx_count = (size_t)P * XSZ + A2 + NLO + NHI + A1;
     static constexpr size_t bytes = cplx_count * 2 * sizeof(Real) + (size_t)NTHR * sizeof(float);
 };
+
+// Transform of one ring pair (rings ra, ra + 1) from the 16 samples each
+// thread holds, z[j] = x[t + NT j] with x = f^_ra + i f^_rb: the radix-16
+// pass in registers, the two LDS exchanges through xb (the pair's slot), the
+// pruned last stage, and the split into the two rings' spectra, written to
+// the ring-tile-blocked layout.  Every thread of the workgroup calls it (it
+// holds barriers); vmax collects max |F| for the FP16 split.
+template <typename Real, int A, int A2, int WG, int TP>
+__device__ __forceinline__ void fft_pair(cplx<Real> (&z)[16], cplx<Real>* xb, const cplx<Real>* tA2,
+                                         const cplx<Real>* tLo, const cplx<Real>* tHi, const cplx<Real>* w3, int t,
+                                         int ra, Real* Fimg, int M, float& vmax) {
+    using C = cplx<Real>;
+    using L = FftLds<Real, A, A2, WG, TP>;
+    constexpr int NT = L::NT, A1 = L::A1, Q = L::Q, KG = L::KG, S1 = L::S1, S2 = L::S2, NLO = L::NLO;
+    const int a1 = t % A1;
+    const int q = t / A1;
+    SmallDft<Real, 16>::run(z);
+    // then W_A2^(q k')
+#pragma unroll
+    for (int k = 1; k < 16; ++k) {
+        const C w = tA2[(q * k) % A2];
+        z[k] = mulw(z[k], w.x, w.y);
+    }
+    __syncthreads();  // all reads of the gathered samples are done
+#pragma unroll
+    for (int k = 0; k < 16; ++k) xb[k * S1 + t] = z[k];
+    __syncthreads();
+    // phase 2: for k' in this thread's group, length-Q DFT over q, then W_A^(a1 k2)
+    C y[KG][Q];
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk) {
+        const int kp = q * KG + kk;
+#pragma unroll
+        for (int qq = 0; qq < Q; ++qq) y[kk][qq] = xb[kp * S1 + a1 + A1 * qq];
+        SmallDft<Real, Q>::run(y[kk]);
+        if constexpr (A1 <= 16) {
+            // W_A^(a1 kp) W_A^(16 a1 k2); A1 divides 16, so the second factor is a W_A2 table entry
+            const int x0 = a1 * kp;  // < 16 A1 <= A
+            const C h = tHi[x0 / NLO], l = tLo[x0 % NLO];
+            const C b = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) {
+                const C u = tA2[a1 * k2 * (16 / A1)];  // 16 a1 k2 / A1 < A2
+                const C w = C{b.x * u.x - b.y * u.y, b.x * u.y + b.y * u.x};
+                y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
+            }
+        } else {
+#pragma unroll
+            for (int k2 = 0; k2 < Q; ++k2) {
+                const int x = a1 * (kp + 16 * k2);  // < A
+                const C h = tHi[x / NLO], l = tLo[x % NLO];
+                const C w = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
+                y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KG; ++kk)
+#pragma unroll
+        for (int k2 = 0; k2 < Q; ++k2) xb[((q * KG + kk) + 16 * k2) * S2 + a1] = y[kk][k2];
+    __syncthreads();
+    // phase 3: bins m (k1 = 0) and A - m (k1 = A1 - 1), then split the two rings
+    const int rt = ra / zm::kRingTile, ri = ra % zm::kRingTile;
+    Real* Fo = Fimg + (size_t)rt * M * 2 * zm::kRingTile + ri;
+    for (int m = t; m < M; m += NT) {
+        C pm = {(Real)0, (Real)0};
+#pragma unroll 4
+        for (int i = 0; i < A1; ++i) pm = pm + xb[m * S2 + i];
+        C nm = pm;
+        if (m > 0) {
+            nm = C{(Real)0, (Real)0};
+            const int row = A2 - m;
+            if constexpr (A1 == 16) {
+                // exp(+2 pi i a1 / 16) as immediates
+                constexpr double c16[16] = {1, kC1, kR2, kS1, 0, -kS1, -kR2, -kC1, -1, -kC1, -kR2, -kS1, 0, kS1, kR2, kC1};
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const C v = xb[row * S2 + i];
+                    const Real wc = (Real)c16[i], ws = (Real)c16[(i + 12) % 16];  // sin = cos(. - pi/2)
+                    nm.x += v.x * wc - v.y * ws;
+                    nm.y += v.x * ws + v.y * wc;
+                }
+            } else {
+#pragma unroll 4
+                for (int i = 0; i < A1; ++i) {
+                    const C v = xb[row * S2 + i];
+                    const C w = w3[i];
+                    nm.x += v.x * w.x - v.y * w.y;
+                    nm.y += v.x * w.y + v.y * w.x;
+                }
+            }
+        }
+        // ring a: (X[m] + conj X[A-m]) / 2 ; ring b: (X[m] - conj X[A-m]) / (2 i)
+        const Real fax = (Real)0.5 * (pm.x + nm.x), fay = (Real)0.5 * (pm.y - nm.y);
+        const Real fbx = (Real)0.5 * (pm.y + nm.y), fby = (Real)0.5 * (nm.x - pm.x);
+        vmax = fmaxf(vmax, fmaxf(fmaxf((float)fabs((double)fax), (float)fabs((double)fay)),
+                                 fmaxf((float)fabs((double)fbx), (float)fabs((double)fby))));
+        Real* o = Fo + (size_t)m * 2 * zm::kRingTile;  // ri even: 2-element aligned
+        *reinterpret_cast<Pair2<Real>*>(o) = Pair2<Real>{fax, fbx};
+        *reinterpret_cast<Pair2<Real>*>(o + zm::kRingTile) = Pair2<Real>{fay, fby};
+    }
+}
 
 // One workgroup-tile of the fused resample + FFT: rings
 // [tile * 2 PAIRS, (tile + 1) * 2 PAIRS) of frame img.  smem holds
@@ -387,7 +528,8 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
                 const int a_h = (rest / S::RPR) * 4 + (tid & 3);
                 const double sr_h = kHFixed ? sr_h0 : (rbase + ri_h < R ? spx[rbase + ri_h] : 0.0);
                 const double ci = trig[2 * kStep * i], si = trig[2 * kStep * i + 1];
-                const double cv = c0 * ci - s0 * si, sv = s0 * ci + c0 * si;
+                double cv, sv;
+                rotate_pair(c0, s0, ci, si, cv, sv);
                 double ch, sh;
                 if constexpr (kHFixed) {
                     // lane RPR * k of the wave holds V angle (first V angle of the wave) + k
@@ -404,12 +546,12 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
                 const int ri_p = p_v ? ri_v : ri_h, a_p = p_v ? a_v : a_h;
                 const int ri_q = q_v ? ri_v : ri_h, a_q = q_v ? a_v : a_h;
                 const double sr_p = p_v ? sr_v : sr_h, sr_q = q_v ? sr_v : sr_h;
-                const double pc = sr_p * (p_v ? cv : ch), ps = sr_p * (p_v ? sv : sh);
-                const double qc = sr_q * (q_v ? cv : ch), qs = sr_q * (q_v ? sv : sh);
-                // the four quarter turns of (c, s): x = cx + (c, -s, -c, s), y = cy - (s, c, -s, -c);
-                // with 2 cx = W - 1 and 2 cy = H - 1 the negated offsets are mirrors
-                const Coord<Real> xa = split_coord<Real>(cx + pc), yb = split_coord<Real>(cy + ps);
-                const Coord<Real> xb2 = split_coord<Real>(cx + qs), yd = split_coord<Real>(cy + qc);
+                const double cp = p_v ? cv : ch, sp = p_v ? sv : sh;
+                const double cq = q_v ? cv : ch, sq = q_v ? sv : sh;
+                // the four quarter turns of (c, s) as in sample_pos: x = cx + (c, -s, -c, s),
+                // y = cy - (s, c, -s, -c); the negated offsets are mirrors
+                const Coord<Real> xa = split_coord<Real>(fma(sr_p, cp, cx)), yb = split_coord<Real>(fma(sr_p, sp, cy));
+                const Coord<Real> xb2 = split_coord<Real>(fma(sr_q, sq, cx)), yd = split_coord<Real>(fma(sr_q, cq, cy));
                 const Coord<Real> xs[4] = {xa, mirror_coord(xb2, W - 1), mirror_coord(xa, W - 1), xb2};
                 const Coord<Real> ys[4] = {mirror_coord(yb, H - 1), mirror_coord(yd, H - 1), yb, yd};
                 const bool in_p = rbase + ri_p < R, in_q = rbase + ri_q < R;
@@ -441,92 +583,7 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
 #pragma unroll
             for (int j = 0; j < 16; ++j) z[j] = xb[t + NT * j];
         }
-        SmallDft<Real, 16>::run(z);
-        // then W_A2^(q k')
-#pragma unroll
-        for (int k = 1; k < 16; ++k) {
-            const C w = tA2[(q * k) % A2];
-            z[k] = mulw(z[k], w.x, w.y);
-        }
-        __syncthreads();  // all reads of the gathered samples are done
-#pragma unroll
-        for (int k = 0; k < 16; ++k) xb[k * S1 + t] = z[k];
-        __syncthreads();
-        // phase 2: for k' in this thread's group, length-Q DFT over q, then W_A^(a1 k2)
-        C y[KG][Q];
-#pragma unroll
-        for (int kk = 0; kk < KG; ++kk) {
-            const int kp = q * KG + kk;
-#pragma unroll
-            for (int qq = 0; qq < Q; ++qq) y[kk][qq] = xb[kp * S1 + a1 + A1 * qq];
-            SmallDft<Real, Q>::run(y[kk]);
-            if constexpr (A1 <= 16) {
-                // W_A^(a1 kp) W_A^(16 a1 k2); A1 divides 16, so the second factor is a W_A2 table entry
-                const int x0 = a1 * kp;  // < 16 A1 <= A
-                const C h = tHi[x0 / NLO], l = tLo[x0 % NLO];
-                const C b = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
-#pragma unroll
-                for (int k2 = 0; k2 < Q; ++k2) {
-                    const C u = tA2[a1 * k2 * (16 / A1)];  // 16 a1 k2 / A1 < A2
-                    const C w = C{b.x * u.x - b.y * u.y, b.x * u.y + b.y * u.x};
-                    y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
-                }
-            } else {
-#pragma unroll
-                for (int k2 = 0; k2 < Q; ++k2) {
-                    const int x = a1 * (kp + 16 * k2);  // < A
-                    const C h = tHi[x / NLO], l = tLo[x % NLO];
-                    const C w = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
-                    y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
-                }
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int kk = 0; kk < KG; ++kk)
-#pragma unroll
-            for (int k2 = 0; k2 < Q; ++k2) xb[((q * KG + kk) + 16 * k2) * S2 + a1] = y[kk][k2];
-        __syncthreads();
-        // phase 3: bins m (k1 = 0) and A - m (k1 = A1 - 1), then split the two rings
-        const int rt = ra / zm::kRingTile, ri = ra % zm::kRingTile;
-        Real* Fo = Fimg + (size_t)rt * M * 2 * zm::kRingTile + ri;
-        for (int m = t; m < M; m += NT) {
-            C pm = {(Real)0, (Real)0};
-#pragma unroll 4
-            for (int i = 0; i < A1; ++i) pm = pm + xb[m * S2 + i];
-            C nm = pm;
-            if (m > 0) {
-                nm = C{(Real)0, (Real)0};
-                const int row = A2 - m;
-                if constexpr (A1 == 16) {
-                    // exp(+2 pi i a1 / 16) as immediates
-                    constexpr double c16[16] = {1, kC1, kR2, kS1, 0, -kS1, -kR2, -kC1, -1, -kC1, -kR2, -kS1, 0, kS1, kR2, kC1};
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) {
-                        const C v = xb[row * S2 + i];
-                        const Real wc = (Real)c16[i], ws = (Real)c16[(i + 12) % 16];  // sin = cos(. - pi/2)
-                        nm.x += v.x * wc - v.y * ws;
-                        nm.y += v.x * ws + v.y * wc;
-                    }
-                } else {
-#pragma unroll 4
-                    for (int i = 0; i < A1; ++i) {
-                        const C v = xb[row * S2 + i];
-                        const C w = w3[i];
-                        nm.x += v.x * w.x - v.y * w.y;
-                        nm.y += v.x * w.y + v.y * w.x;
-                    }
-                }
-            }
-            // ring a: (X[m] + conj X[A-m]) / 2 ; ring b: (X[m] - conj X[A-m]) / (2 i)
-            const Real fax = (Real)0.5 * (pm.x + nm.x), fay = (Real)0.5 * (pm.y - nm.y);
-            const Real fbx = (Real)0.5 * (pm.y + nm.y), fby = (Real)0.5 * (nm.x - pm.x);
-            vmax = fmaxf(vmax, fmaxf(fmaxf((float)fabs((double)fax), (float)fabs((double)fay)),
-                                     fmaxf((float)fabs((double)fbx), (float)fabs((double)fby))));
-            Real* o = Fo + (size_t)m * 2 * zm::kRingTile;  // ri even: 2-element aligned
-            *reinterpret_cast<Pair2<Real>*>(o) = Pair2<Real>{fax, fbx};
-            *reinterpret_cast<Pair2<Real>*>(o + zm::kRingTile) = Pair2<Real>{fay, fby};
-        }
+        fft_pair<Real, A, A2, WG, TP>(z, xb, tA2, tLo, tHi, w3, t, ra, Fimg, M, vmax);
     }
     if (fmaxbuf != nullptr) {
         red[tid] = vmax;

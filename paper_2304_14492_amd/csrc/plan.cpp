@@ -2,10 +2,12 @@
 // tables, workspace layout and the C entry points declared in zm.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
 
+#include "stage_body.h"
 #include "zm_internal.h"
 
 namespace zm {
@@ -125,6 +127,15 @@ zm_status note_call(zm_plan_s* p, hipStream_t s, bool may_create) {
     return ZM_OK;
 }
 
+// The staged resample + FFT serves FP32-family plans with A = 4096 when the
+// environment variable ZM_STAGED is "1" at plan creation (it is slower than
+// the direct gather on MI355X as built; kept, tested, for the comparison).
+constexpr int kStageThreads = 1024;
+static bool stage_enabled() {
+    const char* v = std::getenv("ZM_STAGED");
+    return v && v[0] == '1' && v[1] == '\0';
+}
+
 // ---- Static scratch for zm_moments_static (callers that cannot allocate) ----
 // The spectra workspace of zm_moments_static lives in this array; every
 // device the library runs on holds its own copy until the process ends.  Its
@@ -166,7 +177,7 @@ static void free_plan(zm_plan_s* p) {
     if (!p) return;
     for (auto& d : p->done) (void)hipEventDestroy(d.second);
     void* bufs[] = {p->d_spx, p->d_trig, p->d_tw, p->d_table, p->d_jac, p->d_thi,
-                    p->d_tlo, p->d_rowscale, p->d_items, p->d_rowmap};
+                    p->d_tlo, p->d_rowscale, p->d_items, p->d_rowmap, p->d_stage_win, p->d_stage_rows};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     delete p;
@@ -197,6 +208,7 @@ static size_t workspace_bytes(const zm_plan_s* p, int batch) {
 static bool moments_supported(const zm_plan_s* p) {
     return p->n_max <= kMaxMomentOrder && polar_fft_supported(p->dtype, p->A, p->A2);
 }
+
 
 }  // namespace zm
 
@@ -433,6 +445,28 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
         }
         ZM_TRYHIP(hipMemcpy(p->d_items, p->items.data(), p->items.size() * sizeof(zm_item), hipMemcpyHostToDevice));
         ZM_TRYHIP(hipMemcpy(p->d_rowmap, rowmap.data(), rowmap.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
+    if (with_moments && p->dtype != ZM_F64 && p->A == 4096 && stage_enabled()) {
+        std::vector<zmk::StageWin> wins;
+        std::vector<int> rows;
+        bool ok = false;
+        switch (p->A2) {
+            case 16: ok = zmk::stage_windows<4096, 16, kStageThreads>(p->H, p->W, p->R, p->Rp, p->cx, p->cy, spx, trig, wins, rows); break;
+            case 32: ok = zmk::stage_windows<4096, 32, kStageThreads>(p->H, p->W, p->R, p->Rp, p->cx, p->cy, spx, trig, wins, rows); break;
+            case 64: ok = zmk::stage_windows<4096, 64, kStageThreads>(p->H, p->W, p->R, p->Rp, p->cx, p->cy, spx, trig, wins, rows); break;
+            case 128: ok = zmk::stage_windows<4096, 128, kStageThreads>(p->H, p->W, p->R, p->Rp, p->cx, p->cy, spx, trig, wins, rows); break;
+            case 256: ok = zmk::stage_windows<4096, 256, kStageThreads>(p->H, p->W, p->R, p->Rp, p->cx, p->cy, spx, trig, wins, rows); break;
+            default: break;
+        }
+        if (ok) {
+            zmk::StageWin* dw = nullptr;
+            ZM_TRY(dev_alloc(&dw, wins.size(), &total));
+            p->d_stage_win = dw;
+            ZM_TRY(dev_alloc(&p->d_stage_rows, rows.size(), &total));
+            ZM_TRYHIP(hipMemcpy(dw, wins.data(), wins.size() * sizeof(zmk::StageWin), hipMemcpyHostToDevice));
+            ZM_TRYHIP(hipMemcpy(p->d_stage_rows, rows.data(), rows.size() * sizeof(int), hipMemcpyHostToDevice));
+            p->stage_nthr = kStageThreads;
+        }
     }
     {
         hipError_t e = launch_zrp_table(p, d_rho, d_ck, nullptr);

@@ -27,12 +27,62 @@
 #include <hip/hip_runtime.h>
 
 #include "fft_body.h"
+#include "stage_body.h"
 
 namespace {
 
 using namespace zmk;
 
 constexpr int kWgSize = 512;
+
+// Staged variant (FP32 frames, A = 4096): one round of 2P rings per
+// workgroup of kStageWg threads, windows from the plan.
+constexpr int kStageWg = 1024;
+
+template <int A2>
+hipError_t launch_staged(const zm_plan_s* p, const void* src, long long stride, int batch, void* F, float* fmax,
+                         hipStream_t s) {
+    constexpr int A = 4096;
+    using SS = StageShape<A, A2, kStageWg>;
+    const int gx = p->Rp / (2 * SS::P);
+    const int G = gx * batch;
+    const int G8 = (G + 7) / 8 * 8;
+    FftArgs<float> g;
+    g.src = (const float*)src;
+    g.src_stride = stride;
+    g.H = p->H;
+    g.W = p->W;
+    g.cx = p->cx;
+    g.cy = p->cy;
+    g.safe_s = fmin(p->cx, p->cy) - 1e-6;
+    g.R = p->R;
+    g.Rp = p->Rp;
+    g.M = p->n_max + 1;
+    g.from_polar = 0;
+    g.spx = p->d_spx;
+    g.trig = p->d_trig;
+    g.tw = (const float*)p->d_tw;
+    g.F = (float*)F;
+    g.fmaxbuf = fmax;
+    StageArgs sa;
+    sa.win = (const StageWin*)p->d_stage_win;
+    sa.rows = p->d_stage_rows;
+    sa.vec4 = (p->W % 4 == 0 && stride % 4 == 0 && ((uintptr_t)src & 15) == 0) ? 1 : 0;
+    hipLaunchKernelGGL((polar_fft_staged_kernel<A, A2, kStageWg>), dim3(G8), dim3(kStageWg), 0, s, g, sa, gx, G);
+    return hipGetLastError();
+}
+
+hipError_t dispatch_staged(const zm_plan_s* p, const void* src, long long stride, int batch, void* F, float* fmax,
+                           hipStream_t s) {
+    switch (p->A2) {
+        case 16: return launch_staged<16>(p, src, stride, batch, F, fmax, s);
+        case 32: return launch_staged<32>(p, src, stride, batch, F, fmax, s);
+        case 64: return launch_staged<64>(p, src, stride, batch, F, fmax, s);
+        case 128: return launch_staged<128>(p, src, stride, batch, F, fmax, s);
+        case 256: return launch_staged<256>(p, src, stride, batch, F, fmax, s);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 template <typename Real, int A, int A2>
 hipError_t launch_one(const zm_plan_s* p, const void* src, long long stride, int batch, void* F, float* fmax,
@@ -121,6 +171,8 @@ namespace zm {
 hipError_t launch_polar_fft(const zm_plan_s* p, const void* img, long long stride, int batch, void* F,
                             float* fmax, int from_polar, hipStream_t s) {
     if (p->dtype == ZM_F64) return dispatch_a<double>(p, img, stride, batch, F, fmax, from_polar, s);
+    if (p->stage_nthr == kStageWg && p->A == 4096 && !from_polar)
+        return dispatch_staged(p, img, stride, batch, F, fmax, s);
     return dispatch_a<float>(p, img, stride, batch, F, fmax, from_polar, s);
 }
 

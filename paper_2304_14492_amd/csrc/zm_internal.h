@@ -114,6 +114,12 @@ struct zm_plan_s {
     float* d_rowscale = nullptr;         // per operand row: factor undoing the F16 row scaling
     zm_item* d_items = nullptr;
     int* d_rowmap = nullptr;             // operand row -> canonical idx (-1 for padding)
+    // staged resample + FFT (frame pixels through LDS): workgroup size, 0 when
+    // the plan uses the direct gather; per (round, sector) staging windows and
+    // their row entries, laid out at plan time
+    int stage_nthr = 0;
+    void* d_stage_win = nullptr;
+    int* d_stage_rows = nullptr;
     size_t resident = 0;
 
     // What zm_destroy checks before freeing (guarded by mu): the completion

@@ -35,6 +35,7 @@ static void check_null_arguments(void) {
     CHECK(zm_plan_info(NULL, NULL) == ZM_EINVAL);
     CHECK(zm_radial_table(NULL, NULL, 0) == ZM_EINVAL);
     CHECK(zm_ring_nodes(NULL, NULL, NULL, 0) == ZM_EINVAL);
+    CHECK(zm_operand_table(NULL, NULL, 0) == ZM_EINVAL);
     CHECK(zm_workspace_size(NULL, 1, &bytes) == ZM_EINVAL);
     CHECK(zm_moments(NULL, NULL, 1, 0, NULL, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_moments_static(NULL, NULL, 1, 0, NULL, NULL) == ZM_EINVAL);

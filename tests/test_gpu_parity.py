@@ -293,3 +293,28 @@ def test_argument_errors(zm):
     st = zm._lib.zm_moments(plan.handle, zm._vp(x.data_ptr()), 1, 64 * 64, zm._vp(out.data_ptr()),
                             zm._vp(ws.data_ptr()), 16, None)
     assert st == zm.ZM_EINVAL  # and so does the library
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f16x2"])
+def test_staged_gather_bit_identical(zm, dtype, monkeypatch):
+    # the staged resample + FFT (frame pixels through LDS, plan-time windows;
+    # ZM_STAGED=1 at plan creation) forms the same samples and the same
+    # transform as the direct gather: bit-identical spectra and moments at 4K
+    H, W = 2160, 3840
+    frames = np.stack([synth.make_frame(synth.FrameSpec(H, W, blobs=8, polygons=4, zero_outside=False), 30 + i)
+                       for i in range(3)])
+    x = torch.from_numpy(frames).cuda()
+    monkeypatch.setenv("ZM_STAGED", "1")
+    ps = zm.Plan(200, H, W, dtype=dtype, rings=1080, angles=4096)
+    monkeypatch.setenv("ZM_STAGED", "0")
+    pd = zm.Plan(200, H, W, dtype=dtype, rings=1080, angles=4096)
+    assert ps.info.resident_bytes > pd.info.resident_bytes  # the windows are resident
+    wss, wsd = ps.workspace(3).zero_(), pd.workspace(3).zero_()  # unused slot bytes compare equal too
+    ps.spectra(x, wss)
+    pd.spectra(x, wsd)
+    Zs, Zd = ps.moments(x), pd.moments(x)
+    torch.cuda.synchronize()
+    assert torch.equal(wss, wsd)
+    assert torch.equal(Zs, Zd)
+    Zo = oracle.moments(frames[0].astype(np.float64), 200, 1080, 4096)
+    assert rel_l2(zm.as_complex(Zs[0]).cpu().numpy().astype(np.complex128), Zo) <= (1e-5 if dtype == "f32" else 1e-4)
