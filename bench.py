@@ -38,10 +38,13 @@ value, unit, ms_per_step, config, ...):
                  rate of the disk pixels
   dedup          moments as image hashes (eq. (16)/(17)) over a synthetic set
                  with planted duplicate groups
+  stability      orthogonality of the radial table to order 500 on
+                 Gauss-Legendre rings (Sec. 3.1), FP64 and the operand forms
 """
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -134,6 +137,20 @@ def projection_entry(dtype, proj_ms, batch):
             "issued_frac": round(issued / (proj_ms / 1e3) / 1e12 / MFMA_PEAK_TFLOPS[dtype], 4),
             "hbm": {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes}}
+
+
+def stability_sweep():
+    """Sec. 3.1 / Fig. 1: orthogonality error of the radial table to order 500
+    on Gauss-Legendre rings (502), FP64 as built on the GPU by eq. (7) and in
+    the projection operand's FP32 / hi+lo BF16 / hi+lo FP16 forms; maximum per
+    band of 50 orders."""
+    import paper_2304_14492_amd as zm
+    from paper_2304_14492_amd import stability
+    plan = zm.Plan(500, 2048, 2048, dtype="f32", rings=502, angles=1024, rule="gauss_legendre")
+    res = stability.sweep(plan)
+    res.pop("curves")
+    res["measure"] = "max over m, n' of |2(n+1) sum_r w_r R_nm R_n'm - delta_nn'|"
+    return res
 
 
 def make_frames(batch):
@@ -388,7 +405,12 @@ def serving(dtype, count, qps, warmup_s):
                 r.t_arrival = 0.0
         dev.warm({(r.H, r.W, r.nmax) for r in reqs})
         sch = serve.Scheduler(dev, budget_bytes=4 << 30, max_inflight=8, max_batch=8)
-        done = serve.run_stream(reqs, sch)
+        gc.collect()
+        gc.disable()  # no collector pauses inside the timed stream
+        try:
+            done = serve.run_stream(reqs, sch)
+        finally:
+            gc.enable()
         st = serve.latency_stats(done, warmup_s=0.0 if burst else warmup_s, by_size=not burst)
         st.update(qps=None if burst else rate, requests=n, peak_budget_bytes=sch.peak_used)
         return st
@@ -426,6 +448,7 @@ def main():
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction timing")
     ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian single-moment timing")
     ap.add_argument("--no-dedup", action="store_true", help="skip the de-duplication timing")
+    ap.add_argument("--no-stability", action="store_true", help="skip the order-500 orthogonality sweep")
     ap.add_argument("--cartesian-only", action="store_true",
                     help="only the Cartesian single-moment timing (prints its JSON object)")
     ap.add_argument("--batch-form-only", action="store_true",
@@ -527,6 +550,9 @@ def main():
         torch.cuda.empty_cache()
         res["cartesian_single_moment"] = cartesian_single_moment()
         print(f"[bench] cartesian: {res['cartesian_single_moment']['roofline']}", file=sys.stderr, flush=True)
+    if not args.no_stability:
+        res["stability"] = stability_sweep()
+        print(f"[bench] stability: {res['stability']['max']}", file=sys.stderr, flush=True)
     if not args.no_dedup:
         torch.cuda.empty_cache()
         res["dedup"] = dedup_throughput()

@@ -8,8 +8,10 @@
 // spectra written by the resample+FFT kernel, blocked by 16-ring tiles:
 // F[(((b * nRT + r / 16) * M + m) * 2 + re|im) * 16 + r % 16].
 //
-// One wave owns a (m, 16- or 32-row) x (32-column) output block; columns are
-// (frame, re|im).  Each lane streams 16-byte rows of both operands straight
+// An output block is (m, 16- or 32-row) x (32 columns); columns are
+// (frame, re|im).  Its rings are summed in four fixed chunks whose partial
+// sums are added in chunk order, by one wave or by four (one per chunk), with
+// the same result.  Each lane streams 16-byte rows of both operands straight
 // from memory; since only the pairing of k between the A and B fragments
 // matters for a contraction, lane group g of every MFMA takes ring
 // k0 + 4 g + v (v = element of the 16-byte vector) for both operands.
@@ -53,22 +55,43 @@ ProjArgs make_proj_args(const zm_plan_s* p, const void* F, const float* fmax, in
 // XCD runs a contiguous range of units.  Units are ordered by m, so the
 // row blocks of one m (which all read the same spectra slice F[., m, ., .])
 // then share one L2 and the slice comes from HBM once.
-template <int DT>
+// A workgroup of four waves: with NP = 1 each wave owns one output block and
+// runs through its rings; with NP = kChunks the four waves share one block,
+// one ring chunk each, and add their partial sums in chunk order.  Either way
+// the moments are the same bits (see project_unit), so the launch picks the
+// split by size: one block per wave while the blocks fill the chip's SIMDs,
+// four waves per block below that (small batches).
+template <int DT, int NP>
 __global__ __launch_bounds__(64 * kWaves) void project_kernel(ProjArgs a, int n_blocks) {
+    __shared__ __attribute__((aligned(16))) char red[NP == 1 ? 16 : chunk_lds_bytes<DT>()];
     const int per_xcd = (int)(gridDim.x / 8);
     const int blk = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-    if (blk >= n_blocks) return;
-    const int unit = blk * kWaves + (threadIdx.x >> 6);
-    if (unit >= a.n_units) return;
-    project_unit<DT>(a, unit, threadIdx.x & 63);
+    if (blk >= n_blocks) return;  // whole workgroups only: the waves of a block meet at barriers
+    if constexpr (NP == 1) {
+        const int unit = blk * kWaves + (threadIdx.x >> 6);
+        if (unit < a.n_units) project_unit<DT, 1>(a, unit, threadIdx.x & 63, 0, true, red);
+    } else {
+        project_unit<DT, NP>(a, blk, threadIdx.x & 63, threadIdx.x >> 6, true, red);
+    }
 }
+
+static_assert(kWaves == kChunks, "a workgroup of one block holds one wave per chunk");
+
+// output blocks from which one wave per block fills the MI355X's 1024 SIMDs
+constexpr int kBlocksOneWave = 1024;
 
 template <int DT>
 hipError_t launch_dt(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
     ProjArgs a = make_proj_args(p, F, fmax, batch, Z, nullptr);
-    const int blocks = (a.n_units + kWaves - 1) / kWaves;
-    const int blocks8 = (blocks + 7) / 8 * 8;
-    hipLaunchKernelGGL((project_kernel<DT>), dim3(blocks8), dim3(64 * kWaves), 0, s, a, blocks);
+    if (a.n_units >= kBlocksOneWave) {
+        const int blocks = (a.n_units + kWaves - 1) / kWaves;
+        const int blocks8 = (blocks + 7) / 8 * 8;
+        hipLaunchKernelGGL((project_kernel<DT, 1>), dim3(blocks8), dim3(64 * kWaves), 0, s, a, blocks);
+    } else {
+        const int blocks = a.n_units;
+        const int blocks8 = (blocks + 7) / 8 * 8;
+        hipLaunchKernelGGL((project_kernel<DT, kChunks>), dim3(blocks8), dim3(64 * kWaves), 0, s, a, blocks);
+    }
     return hipGetLastError();
 }
 

@@ -18,6 +18,23 @@ typedef float float8 __attribute__((ext_vector_type(8)));
 
 constexpr int kWaves = 4;
 
+// The rings of an output block are summed in kChunks contiguous chunks whose
+// partial sums are added in chunk order, ((c0 + c1) + c2) + c3, whichever
+// waves compute them: one wave running through all chunks (NP = 1) or one
+// wave per chunk meeting in LDS (NP = kChunks).  The result is the same bits
+// either way, so a launch can pick the split that suits its size.
+constexpr int kChunks = 4;
+
+// First ring of chunk c: the block's K steps (16 rings, or 32 for the 16-bit
+// splits) dealt out in contiguous runs.
+__device__ __forceinline__ int chunk_edge(int Rp, int step, int c) { return ((Rp / step) * c / kChunks) * step; }
+
+// LDS one output block needs when its chunks are split over waves: [chunk][16][64] values.
+template <int DT>
+constexpr size_t chunk_lds_bytes() {
+    return (size_t)kChunks * 16 * 64 * (DT == ZM_F64 ? sizeof(double) : sizeof(float));
+}
+
 __device__ __forceinline__ int out_index(int n, int m) { return zm::canon_index(n, m); }
 
 
@@ -50,9 +67,18 @@ __device__ __forceinline__ T* zbase(const ProjArgs& a, int fr) {
     return a.Z ? (T*)a.Z + (size_t)fr * a.Mtot * 2 : (T*)((const GP*)(const void*)a.Zptrs)[fr];
 }
 
-// One wave: output block `unit` = (item unit / ncb, column block unit % ncb).
-template <int DT>
-__device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int lane) {
+// Output block `unit` = (item unit / ncb, column block unit % ncb).  With
+// NP = 1 this wave computes the whole block; with NP = kChunks it computes
+// chunk `part`, the NP waves of the block run together in one workgroup and
+// meet at barriers (a wave with valid == false, a block past the end,
+// computes nothing but still reaches them), red is the block's
+// chunk_lds_bytes<DT>() of LDS.
+template <int DT, int NP>
+__device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int lane, int part, bool valid, void* red) {
+    static_assert(NP == 1 || NP == kChunks, "one wave per block or one per chunk");
+    using Acc = typename std::conditional<DT == ZM_F64, doublex4, floatx4>::type;
+    using Val = typename std::conditional<DT == ZM_F64, double, float>::type;
+    if (!valid) unit = 0;
     const zm_item* __restrict__ items = a.items;
     const void* __restrict__ thi = a.thi;
     const void* __restrict__ tlo = a.tlo;
@@ -86,26 +112,60 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
 #pragma unroll
     for (int s = 0; s < 2; ++s) aoff[s] = zm::op_index(it.toff + it.row0 + 16 * s, 0, Rp, kG) + (size_t)li * kG;
 
+    // this wave's chunks [c0, c1) and their rings [kb, ke)
+    constexpr int STEP = (DT == ZM_F64 || DT == ZM_F32) ? 16 : 32;
+    const int c0 = NP == 1 ? 0 : part, c1 = NP == 1 ? kChunks : part + 1;
+    const int kb = chunk_edge(Rp, STEP, c0);
+    const int ke = valid ? chunk_edge(Rp, STEP, c1) : kb;
+    Acc acc[2][2] = {};
+    Acc tot[2][2] = {};  // NP = 1: sum of the finished chunks, in order
+    Val* rd = (Val*)red;
+    // the accumulators hold chunk c: fold them into the total (NP = 1) or
+    // hand them to LDS (NP = kChunks), and clear them for the next chunk
+    auto flush = [&](int c) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if constexpr (NP == 1) {
+                    if (c == 0)
+                        tot[s][u] = acc[s][u];
+                    else
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) tot[s][u][v] = tot[s][u][v] + acc[s][u][v];
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) rd[(c * 16 + (s * 2 + u) * 4 + v) * 64 + lane] = acc[s][u][v];
+                }
+                acc[s][u] = Acc{};
+            }
+    };
+    // chunk c's rings end at ce(c); a wave with valid == false runs no rings
+    auto ce = [&](int c) { return valid ? chunk_edge(Rp, STEP, c + 1) : kb; };
+
+    float fsc[2] = {1.f, 1.f};
     if constexpr (DT == ZM_F64) {
         const double* T = (const double*)thi;
         const double* F = (const double*)Fv;
-        doublex4 acc[2][2] = {};
-        for (int k0 = 0; k0 < Rp; k0 += 16) {
+        int k0 = kb;
+#pragma unroll 1
+        for (int c = c0; c < c1; flush(c), ++c)
+        for (const int kc = ce(c); k0 < kc; k0 += 16) {
             const int kk = k0 + 4 * lg;
-            double a[2][4], b[2][4];
+            double av[2][4], bv[2][4];
 #pragma unroll
             for (int s = 0; s < 2; ++s) {
                 if (s == 1 && !two) break;
                 const double2 x0 = *(const double2*)(T + aoff[s] + (size_t)kk * 16);
                 const double2 x1 = *(const double2*)(T + aoff[s] + (size_t)kk * 16 + 2);
-                a[s][0] = x0.x; a[s][1] = x0.y; a[s][2] = x1.x; a[s][3] = x1.y;
+                av[s][0] = x0.x; av[s][1] = x0.y; av[s][2] = x1.x; av[s][3] = x1.y;
             }
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const size_t fo = boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg;
                 const double2 y0 = *(const double2*)(F + fo);
                 const double2 y1 = *(const double2*)(F + fo + 2);
-                b[u][0] = y0.x; b[u][1] = y0.y; b[u][2] = y1.x; b[u][3] = y1.y;
+                bv[u][0] = y0.x; bv[u][1] = y0.y; bv[u][2] = y1.x; bv[u][3] = y1.y;
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v)
@@ -114,45 +174,36 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
                     if (s == 1 && !two) break;
 #pragma unroll
                     for (int u = 0; u < 2; ++u)
-                        acc[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s][v], b[u][v], acc[s][u], 0, 0, 0);
+                        acc[s][u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[s][v], bv[u][v], acc[s][u], 0, 0, 0);
                 }
         }
-        const int kmrows = (M - 1 - m) / 2 + 1;
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = it.row0 + 16 * s + lg + 4 * v;  // FP64 MFMA output: row lane/16 + 4 v
-                    if ((s == 0 || two) && row < kmrows && fr[u] < B)
-                        zbase<double>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = acc[s][u][v];
-                }
     } else if constexpr (DT == ZM_F32) {
         const float* T = (const float*)thi;
         const float* F = (const float*)Fv;
-        floatx4 acc[2][2] = {};
-        // operand fragments run two ring steps ahead of the MFMAs (Rp is a multiple of 32)
-        float4 a1[2], b1[2], a2[2], b2[2];
-        auto load = [&](int k0, float4* a, float4* b) {
+        // operand fragments run two ring steps ahead of the MFMAs
+        float4 a1[2] = {}, b1[2] = {}, a2[2] = {}, b2[2] = {};
+        auto load = [&](int k0, float4* ar, float4* br) {
             const int kk = k0 + 4 * lg;
-            a[0] = *(const float4*)(T + aoff[0] + (size_t)kk * 16);
-            a[1] = two ? *(const float4*)(T + aoff[1] + (size_t)kk * 16) : float4{0.f, 0.f, 0.f, 0.f};
+            ar[0] = *(const float4*)(T + aoff[0] + (size_t)kk * 16);
+            ar[1] = two ? *(const float4*)(T + aoff[1] + (size_t)kk * 16) : float4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int u = 0; u < 2; ++u) b[u] = *(const float4*)(F + boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg);
+            for (int u = 0; u < 2; ++u) br[u] = *(const float4*)(F + boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg);
         };
-        load(0, a1, b1);
-        load(16, a2, b2);
-        for (int k0 = 0; k0 < Rp; k0 += 16) {
-            const float4 a[2] = {a1[0], a1[1]}, b[2] = {b1[0], b1[1]};
+        if (kb < ke) load(kb, a1, b1);
+        if (kb + 16 < ke) load(kb + 16, a2, b2);
+        int k0 = kb;
+#pragma unroll 1
+        for (int c = c0; c < c1; flush(c), ++c)
+        for (const int kc = ce(c); k0 < kc; k0 += 16) {
+            const float4 ar[2] = {a1[0], a1[1]}, br[2] = {b1[0], b1[1]};
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 a1[u] = a2[u];
                 b1[u] = b2[u];
             }
-            if (k0 + 32 < Rp) load(k0 + 32, a2, b2);
-            const float av[2][4] = {{a[0].x, a[0].y, a[0].z, a[0].w}, {a[1].x, a[1].y, a[1].z, a[1].w}};
-            const float bv[2][4] = {{b[0].x, b[0].y, b[0].z, b[0].w}, {b[1].x, b[1].y, b[1].z, b[1].w}};
+            if (k0 + 32 < ke) load(k0 + 32, a2, b2);
+            const float av[2][4] = {{ar[0].x, ar[0].y, ar[0].z, ar[0].w}, {ar[1].x, ar[1].y, ar[1].z, ar[1].w}};
+            const float bv[2][4] = {{br[0].x, br[0].y, br[0].z, br[0].w}, {br[1].x, br[1].y, br[1].z, br[1].w}};
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
 #pragma unroll
@@ -165,17 +216,6 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
                 }
             }
         }
-        const int kmrows = (M - 1 - m) / 2 + 1;
-#pragma unroll
-        for (int s = 0; s < 2; ++s)
-#pragma unroll
-            for (int u = 0; u < 2; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = it.row0 + 16 * s + 4 * lg + v;
-                    if ((s == 0 || two) && row < kmrows && fr[u] < B)
-                        zbase<float>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = acc[s][u][v];
-                }
     } else {
         // split forms: 16-bit hi/lo operands, K step 32 (8 consecutive rings per lane group)
         using H8 = typename std::conditional<DT == ZM_BF16X2, bf16x8, halfx8>::type;
@@ -183,12 +223,10 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
         const H1* Th = (const H1*)thi;
         const H1* Tl = (const H1*)tlo;
         const float* F = (const float*)Fv;
-        float fsc[2] = {1.f, 1.f};
         if constexpr (DT == ZM_F16X2) {
 #pragma unroll
             for (int u = 0; u < 2; ++u) fsc[u] = f16_frame_scale(fmaxbuf[fr[u] < B ? fr[u] : B - 1]);
         }
-        floatx4 acc[2][2] = {};
         // raw operand fragments of ring step k0 + 32 are loaded while step k0 runs
         H8 nah[2] = {}, nal[2] = {};
         float4 ny[2][2];
@@ -207,8 +245,11 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
                 ny[u][1] = *(const float4*)(F + fo + 4);
             }
         };
-        load(0);
-        for (int k0 = 0; k0 < Rp; k0 += 32) {
+        if (kb < ke) load(kb);
+        int k0 = kb;
+#pragma unroll 1
+        for (int c = c0; c < c1; flush(c), ++c)
+        for (const int kc = ce(c); k0 < kc; k0 += 32) {
             H8 ah[2], al[2], bh[2], bl[2];
             float4 yy[2][2];
 #pragma unroll
@@ -218,7 +259,7 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
                 yy[s2][0] = ny[s2][0];
                 yy[s2][1] = ny[s2][1];
             }
-            if (k0 + 32 < Rp) load(k0 + 32);
+            if (k0 + 32 < ke) load(k0 + 32);
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
                 const float4 y0 = yy[u][0], y1 = yy[u][1];
@@ -254,20 +295,39 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
                 }
             }
         }
-        const int kmrows = (M - 1 - m) / 2 + 1;
+    }
+
+    // epilogue: element v of accumulator (s, u) is output row row_of(s, v) of column col[u]
+    const int kmrows = (M - 1 - m) / 2 + 1;
+    auto store = [&](int s, int u, int v, Val val) {
+        // FP64 MFMA output rows are lane / 16 + 4 v, the FP32 ones 4 (lane / 16) + v
+        const int row = it.row0 + 16 * s + (DT == ZM_F64 ? lg + 4 * v : 4 * lg + v);
+        if (valid && (s == 0 || two) && row < kmrows && fr[u] < B) {
+            if constexpr (DT == ZM_F16X2) val = val * rowscale[it.toff + row] / fsc[u];
+            zbase<Val>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = val;
+        }
+    };
+    if constexpr (NP == 1) {
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int u = 0; u < 2; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int row = it.row0 + 16 * s + 4 * lg + v;
-                    if ((s == 0 || two) && row < kmrows && fr[u] < B) {
-                        float val = acc[s][u][v];
-                        if constexpr (DT == ZM_F16X2) val = val * rowscale[it.toff + row] / fsc[u];
-                        zbase<float>(a, fr[u])[(size_t)out_index(m + 2 * row, m) * 2 + (col[u] & 1)] = val;
-                    }
-                }
+                for (int v = 0; v < 4; ++v) store(s, u, v, tot[s][u][v]);
+    } else {
+        __syncthreads();
+        const int v = part;  // the wave of chunk p writes vector element p of every accumulator
+#pragma unroll
+        for (int s = 0; s < 2; ++s)
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int e = (s * 2 + u) * 4 + v;
+                Val sum = rd[(0 * 16 + e) * 64 + lane];
+#pragma unroll
+                for (int w = 1; w < kChunks; ++w) sum += rd[(w * 16 + e) * 64 + lane];
+                store(s, u, v, sum);
+            }
+        __syncthreads();
     }
 }
 

@@ -33,6 +33,11 @@ class Request:
     t_done: float = math.nan
     result: object = None
     nbytes: int = 0
+    # device-side time of the request's launch (seconds; GpuDevice only): the
+    # host-to-device copy, the moment computation, the device-to-host copy
+    t_h2d: float = math.nan
+    t_compute: float = math.nan
+    t_d2h: float = math.nan
 
 
 @dataclass
@@ -145,6 +150,20 @@ def latency_stats(done, warmup_s: float = 0.0, by_size: bool = False):
     span = max(r.t_done for r in done) - min(r.t_arrival for r in done)
     out = _percentiles(lat)
     out["images_per_s"] = float(len(done) / span) if span > 0 else 0.0
+    # where the time goes: waiting for admission (host queue), then from the
+    # launch to the observed completion, split on the device (when measured)
+    # into the copies and the computation; "other" is the rest of that span
+    # (the launch calls, waits between the streams, the polling loop)
+    queue = np.array([r.t_admit - r.t_arrival for r in kept])
+    served = np.array([r.t_done - r.t_admit for r in kept])
+    parts = {"queue": queue, "launch_to_done": served}
+    dev = np.array([[r.t_h2d, r.t_compute, r.t_d2h] for r in kept])
+    if np.all(np.isfinite(dev)):
+        parts.update(h2d=dev[:, 0], compute=dev[:, 1], d2h=dev[:, 2], other=served - dev.sum(axis=1))
+    out["split_ms"] = {k: {"mean": float(v.mean() * 1e3), "p99": float(np.percentile(v, 99) * 1e3)}
+                       for k, v in parts.items()}
+    tail = lat >= np.percentile(lat, 99)
+    out["split_ms_p99_tail"] = {k: float(v[tail].mean() * 1e3) for k, v in parts.items()}
     if by_size:
         sizes = collections.defaultdict(list)
         for r in kept:
@@ -213,6 +232,7 @@ class GpuDevice:
         self.copy_in = torch.cuda.Stream()
         self.copy_out = torch.cuda.Stream()
         self.rr = 0
+        self._events = []  # timing events of retired launches, reused
 
     def plan(self, H, W, nmax):
         key = (H, W, nmax)
@@ -238,35 +258,42 @@ class GpuDevice:
         ws = p.workspace(B)
         Z = torch.empty(B, p.num_moments, 2, dtype=torch.float32, device="cuda")
         host_out = torch.empty(B, p.num_moments, 2, dtype=torch.float32, pin_memory=True)
+        ev = self._events.pop() if self._events else [torch.cuda.Event(enable_timing=True) for _ in range(6)]
         with torch.cuda.stream(self.copy_in):
+            ev[0].record(self.copy_in)
             for i, r in enumerate(ln.reqs):
                 frames[i].copy_(r.frame, non_blocking=True)
-            ev_in = torch.cuda.Event()
-            ev_in.record(self.copy_in)
-        cs.wait_event(ev_in)
+            ev[1].record(self.copy_in)
+        cs.wait_event(ev[1])
+        ev[2].record(cs)
         p.moments(frames, out=Z, workspace=ws, stream=cs)
-        ev_c = torch.cuda.Event()
-        ev_c.record(cs)
-        self.copy_out.wait_event(ev_c)
+        ev[3].record(cs)
+        self.copy_out.wait_event(ev[3])
         with torch.cuda.stream(self.copy_out):
+            ev[4].record(self.copy_out)
             host_out.copy_(Z, non_blocking=True)
-            ev_done = torch.cuda.Event()
-            ev_done.record(self.copy_out)
+            ev[5].record(self.copy_out)
+        ev_done = ev[5]
         # keep device buffers alive until the launch retires
         frames.record_stream(self.copy_in)
         frames.record_stream(cs)
         Z.record_stream(cs)
         Z.record_stream(self.copy_out)
         ws.record_stream(cs)
-        ln.handle = (ev_done, frames, ws, Z, host_out)
+        ln.handle = (ev_done, frames, ws, Z, host_out, ev)
 
     def is_done(self, ln: Launch) -> bool:
         return ln.handle[0].query()
 
     def finish(self, ln: Launch):
-        host_out = ln.handle[4]
+        host_out, ev = ln.handle[4], ln.handle[5]
+        h2d = ev[0].elapsed_time(ev[1]) / 1e3
+        comp = ev[2].elapsed_time(ev[3]) / 1e3
+        d2h = ev[4].elapsed_time(ev[5]) / 1e3
         for i, r in enumerate(ln.reqs):
             r.result = host_out[i]
+            r.t_h2d, r.t_compute, r.t_d2h = h2d, comp, d2h
+        self._events.append(ev)
         ln.handle = None
 
     def warm(self, keys):

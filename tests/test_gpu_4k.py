@@ -72,3 +72,9 @@ def test_4k_batch64_all_moments(zm, frames_and_reference, dtype, tol):
         assert max(r[4] for r in rows) <= errmodel.GATE_SIGMAS, (dtype, i, rows)
     for i in range(DISTINCT, BATCH):
         assert np.array_equal(Z[i], Z[i % DISTINCT]), (dtype, i)
+    # a frame alone gives the same bits (the batch of 64 runs the projection
+    # one wave per output block, a single frame four waves per block)
+    for i in range(2):
+        Zi = plan.moments(dev[i:i + 1])
+        torch.cuda.synchronize()
+        assert torch.equal(Zi[0], Zt[i]), (dtype, i)
