@@ -30,6 +30,12 @@
  * a fault in it surfaces at the caller's next synchronisation (and as
  * ZM_EDEVICE from the next call that synchronises).  zm_last_error()
  * returns a thread-local description of the most recent failure.
+ *
+ * Diagnostics: the environment variable ZM_LOG (read once per process)
+ * selects lines on stderr, "zm: <level>: <text>": 0 or unset = none,
+ * 1 = every failure (the zm_last_error text), 2 = also plan and batch
+ * set-up (grid sizes, resident and workspace bytes, tuned batch shape),
+ * 3 = also every call that enqueues device work.
  */
 #ifndef ZM_H_
 #define ZM_H_
@@ -190,6 +196,18 @@ zm_status zm_project(zm_plan_t plan, int batch, void* d_Z, void* d_ws, size_t ws
 zm_status zm_moments_static(zm_plan_t plan, const void* d_images, int batch, long long image_stride, void* d_Z,
                             zm_stream_t stream);
 size_t zm_static_scratch_bytes(void);
+
+/* Screening of the moments of eq. (1) for non-finite values: d_counts[b]
+ * receives how many of frame b's 2 * num_moments stored values (re and im)
+ * are NaN or +-Inf; 0 means every moment of the frame is finite.  A NaN or
+ * Inf pixel that the resampler reads (within D/2 + 1.5 px of the centre)
+ * makes moments non-finite; pixels it never reads do not matter.
+ *   d_Z      : device pointer, zm_moments' output for `batch` frames of this
+ *              plan, [batch][num_moments][2], float or double (ZM_F64).
+ *   d_counts : device pointer to int[batch], overwritten.
+ * Asynchronous on `stream`; allocates nothing.  Errors: ZM_EINVAL (null
+ * plan or pointers, batch < 0 or > 65535), ZM_EDEVICE (launch failure). */
+zm_status zm_count_nonfinite(zm_plan_t plan, const void* d_Z, int batch, int* d_counts, zm_stream_t stream);
 
 /* Moments from a polar image already on the grid (bypasses the resampler):
  * d_polar is [batch][R][A] (float, or double for ZM_F64). */

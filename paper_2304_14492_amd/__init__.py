@@ -80,6 +80,7 @@ _SIGS = {
     "zm_moments_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "zm_moments_static": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp]),
     "zm_static_scratch_bytes": (_sz, []),
+    "zm_count_nonfinite": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "zm_spectra": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _sz, _vp]),
     "zm_project": (ctypes.c_int, [_vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
     "zm_reconstruct": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_int, _vp, _vp, _sz, _vp]),
@@ -351,6 +352,23 @@ class Plan:
                                       frames.stride(0) if B > 1 else self.H * self.W, _vp(out.data_ptr()),
                                       _stream_handle(stream)), "zm_moments_static")
         return out[0] if squeeze else out
+
+    def count_nonfinite(self, Z, counts=None, stream=None):
+        """zm_count_nonfinite: per frame, how many of the moment values in Z
+        ([B, num_moments, 2] or [num_moments, 2], as moments() returns) are
+        NaN or +-Inf.  Returns an int32 CUDA tensor [B] (asynchronous)."""
+        import torch
+        if Z.dim() == 2:
+            Z = Z.unsqueeze(0)
+        B = Z.shape[0]
+        _need(Z, "Z", shape=(B, self.num_moments, 2), dtype=self._real_dtype(), device=self.device)
+        if counts is None:
+            counts = torch.empty(B, dtype=torch.int32, device=Z.device)
+            _keep_alive(stream, counts)
+        _need(counts, "counts", shape=(B,), dtype=torch.int32, device=self.device)
+        _check(_lib.zm_count_nonfinite(self._h, _vp(Z.data_ptr()), B, _vp(counts.data_ptr()), _stream_handle(stream)),
+               "zm_count_nonfinite")
+        return counts
 
     def _check_frames(self, frames):
         if frames.dim() != 3 or frames.shape[1] != self.H or frames.shape[2] != self.W:

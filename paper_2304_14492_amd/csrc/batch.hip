@@ -883,6 +883,9 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         destroy_batch(b);
         return st;
     }
+    log_msg(kLogInfo, "batch %p: %d jobs, %d queue items, %zu device bytes; grid %d, item order %d, %d FFT round(s) "
+        "per item%s%s", (void*)b, njobs, b->n_items, b->d_bytes, b->grid, b->order, b->rounds,
+        (flags & ZM_BATCH_AUTOTUNE) ? " (tuned)" : "", (flags & ZM_BATCH_NO_GRAPH) ? "" : ", graph captured");
     *out = b;
     return ZM_OK;
 }
@@ -912,6 +915,7 @@ zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
         if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
     }
     ZM_HIP(hipEventRecord(b->done, s));
+    log_msg(kLogDebug, "zm_batch_run: batch %p, stream %p", (void*)b, stream);
     return ZM_OK;
 }
 

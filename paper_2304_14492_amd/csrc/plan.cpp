@@ -2,6 +2,8 @@
 // tables, workspace layout and the C entry points declared in zm.h.
 #include <algorithm>
 #include <cmath>
+#include <cstdarg>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <string>
@@ -14,15 +16,40 @@ namespace zm {
 
 static thread_local std::string g_err;
 
-void set_error(const std::string& msg) { g_err = msg; }
+int log_level() {
+    static const int level = [] {
+        const char* v = std::getenv("ZM_LOG");
+        const int l = v ? std::atoi(v) : 0;
+        return l < 0 ? 0 : (l > kLogDebug ? kLogDebug : l);
+    }();
+    return level;
+}
+
+void log_msg(int level, const char* fmt, ...) {
+    if (level > log_level()) return;
+    static const char* const kName[] = {"", "error", "info", "debug"};
+    char line[1024];
+    int n = std::snprintf(line, sizeof line, "zm: %s: ", kName[level]);
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(line + n, sizeof line - n - 1, fmt, ap);
+    va_end(ap);
+    std::strcat(line, "\n");
+    std::fputs(line, stderr);  // one write per line, so lines of concurrent threads do not interleave
+}
+
+void set_error(const std::string& msg) {
+    g_err = msg;
+    log_msg(kLogError, "%s", msg.c_str());
+}
 
 zm_status fail(zm_status s, const std::string& msg) {
-    g_err = msg;
+    set_error(msg);
     return s;
 }
 
 zm_status hip_fail(hipError_t e, const char* what) {
-    g_err = std::string(what) + ": " + hipGetErrorString(e);
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
     return e == hipErrorOutOfMemory ? ZM_ENOMEM : ZM_EDEVICE;
 }
 
@@ -492,6 +519,10 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
     cleanup_tmp();
     p->resident = total;
     *out = p;
+    log_msg(kLogInfo, "plan %p: n_max %d, %d x %d frames, %d rings (%d padded) x %d angles, dtype %d, %s rings, device %d, "
+        "%zu resident bytes, %zu workspace bytes per frame", (void*)p, p->n_max, p->H, p->W, p->R, p->Rp, p->A,
+        (int)p->dtype, p->rule == ZM_RING_GAUSS_LEGENDRE ? "Gauss-Legendre" : "midpoint", p->device, p->resident,
+        workspace_bytes(p, 1) - workspace_bytes(p, 0));
     return ZM_OK;
 }
 
@@ -597,8 +628,9 @@ static zm_status run_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size
 }
 
 // Marks the completion of the call's work on the plan (for zm_destroy).
-static zm_status noted(zm_status st, zm_plan_t p, int batch, zm_stream_t stream) {
+static zm_status noted(zm_status st, zm_plan_t p, int batch, zm_stream_t stream, const char* what) {
     if (st != ZM_OK || batch <= 0) return st;
+    log_msg(kLogDebug, "%s: plan %p, batch %d, stream %p", what, (void*)p, batch, stream);
     ZM_DEVICE(p->device);
     return note_call(p, (hipStream_t)stream);
 }
@@ -607,11 +639,12 @@ zm_status zm_spectra(zm_plan_t p, const void* d_images, int batch, long long ima
                      size_t ws_bytes, zm_stream_t stream) {
     if (p && batch > 1 && image_stride < (long long)p->H * p->W)
         return fail(ZM_EINVAL, "image_stride must be >= H * W");
-    return noted(run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0), p, batch, stream);
+    return noted(run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0), p, batch, stream,
+                 "zm_spectra");
 }
 
 zm_status zm_project(zm_plan_t p, int batch, void* d_Z, void* d_ws, size_t ws_bytes, zm_stream_t stream) {
-    return noted(run_project(p, batch, d_Z, d_ws, ws_bytes, stream), p, batch, stream);
+    return noted(run_project(p, batch, d_Z, d_ws, ws_bytes, stream), p, batch, stream, "zm_project");
 }
 
 zm_status zm_moments(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_Z, void* d_ws,
@@ -621,7 +654,7 @@ zm_status zm_moments(zm_plan_t p, const void* d_images, int batch, long long ima
         return fail(ZM_EINVAL, "image_stride must be >= H * W");
     zm_status st = run_spectra(p, d_images, batch, image_stride, d_ws, ws_bytes, stream, 0);
     if (st == ZM_OK) st = run_project(p, batch, d_Z, d_ws, ws_bytes, stream);
-    return noted(st, p, batch, stream);
+    return noted(st, p, batch, stream, "zm_moments");
 }
 
 zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_Z, void* d_ws, size_t ws_bytes,
@@ -630,7 +663,7 @@ zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_
     if (batch > 0 && !d_Z) return fail(ZM_EINVAL, "null output pointer");
     zm_status st = run_spectra(p, d_polar, batch, (long long)p->R * p->A, d_ws, ws_bytes, stream, 1);
     if (st == ZM_OK) st = run_project(p, batch, d_Z, d_ws, ws_bytes, stream);
-    return noted(st, p, batch, stream);
+    return noted(st, p, batch, stream, "zm_moments_polar");
 }
 
 size_t zm_static_scratch_bytes(void) { return kStaticScratchBytes; }
@@ -657,7 +690,20 @@ zm_status zm_moments_static(zm_plan_t p, const void* d_images, int batch, long l
     st = run_spectra(p, d_images, batch, image_stride, ws, kStaticScratchBytes, stream, 0);
     if (st == ZM_OK) st = run_project(p, batch, d_Z, ws, kStaticScratchBytes, stream);
     if (st != ZM_OK) return st;
+    log_msg(kLogDebug, "zm_moments_static: plan %p, batch %d, stream %p", (void*)p, batch, stream);
     return note_call(p, (hipStream_t)stream, false);
+}
+
+zm_status zm_count_nonfinite(zm_plan_t p, const void* d_Z, int batch, int* d_counts, zm_stream_t stream) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch < 0 || batch > 65535) return fail(ZM_EINVAL, "batch must be in [0, 65535]");
+    if (batch == 0) return ZM_OK;
+    if (!d_Z || !d_counts) return fail(ZM_EINVAL, "null moments or counts pointer");
+    ZM_DEVICE(p->device);
+    hipError_t e = launch_count_nonfinite(p, d_Z, batch, d_counts, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "non-finite count kernel launch");
+    log_msg(kLogDebug, "zm_count_nonfinite: plan %p, batch %d, stream %p", (void*)p, batch, stream);
+    return ZM_OK;
 }
 
 zm_status zm_recon_workspace_size(zm_plan_t p, int batch, size_t* bytes) {
@@ -760,6 +806,7 @@ zm_status zm_destroy(zm_plan_t p) {
             if (hipEventQuery(d.second) == hipErrorNotReady)
                 return fail(ZM_EBUSY, "work enqueued on this plan has not completed; synchronise its stream first");
     }
+    log_msg(kLogInfo, "plan %p destroyed", (void*)p);
     free_plan(p);
     return ZM_OK;
 }

@@ -26,6 +26,8 @@
 // The epilogue writes Z in canonical (n, m) order, [b][idx][re|im].
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "project_body.h"
 
 namespace {
@@ -95,9 +97,47 @@ hipError_t launch_dt(const zm_plan_s* p, const void* F, const float* fmax, int b
     return hipGetLastError();
 }
 
+// Non-finite values among each frame's moments: block (x, b) scans values
+// [x * kScan, (x + 1) * kScan) of frame b (exponent field all ones: NaN or
+// Inf) and adds its count to counts[b], one atomic per wave that found any.
+constexpr int kScanThreads = 256, kScanPer = 4, kScan = kScanThreads * kScanPer;
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void count_nonfinite_kernel(const T* __restrict__ Z, long long per_frame,
+                                                                         int* __restrict__ counts) {
+    using U = typename std::conditional<sizeof(T) == 8, unsigned long long, unsigned>::type;
+    constexpr U kExp = sizeof(T) == 8 ? 0x7ff0000000000000ull : 0x7f800000u;
+    const int b = blockIdx.y;
+    const U* z = reinterpret_cast<const U*>(Z) + (size_t)b * per_frame;
+    const long long base = (long long)blockIdx.x * kScan + threadIdx.x;
+    int bad = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        const long long e = base + (long long)i * kScanThreads;
+        if (e < per_frame) bad += (z[e] & kExp) == kExp ? 1 : 0;
+    }
+    // wave sum by butterfly; lane 0 of a wave with a non-zero count adds it
+    for (int off = 32; off > 0; off >>= 1) bad += __shfl_xor(bad, off, 64);
+    if ((threadIdx.x & 63) == 0 && bad != 0) atomicAdd(counts + b, bad);
+}
+
 }  // namespace
 
 namespace zm {
+
+hipError_t launch_count_nonfinite(const zm_plan_s* p, const void* Z, int batch, int* counts, hipStream_t s) {
+    hipError_t e = launch_zero_u32(reinterpret_cast<unsigned*>(counts), (size_t)batch, s);
+    if (e != hipSuccess) return e;
+    const long long per_frame = 2ll * zm_num_moments(p->n_max);
+    const dim3 grid((unsigned)((per_frame + kScan - 1) / kScan), (unsigned)batch);
+    if (p->dtype == ZM_F64)
+        hipLaunchKernelGGL(count_nonfinite_kernel<double>, grid, dim3(kScanThreads), 0, s, (const double*)Z,
+                           per_frame, counts);
+    else
+        hipLaunchKernelGGL(count_nonfinite_kernel<float>, grid, dim3(kScanThreads), 0, s, (const float*)Z, per_frame,
+                           counts);
+    return hipGetLastError();
+}
 
 hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
     switch (p->dtype) {

@@ -14,6 +14,14 @@
 
 namespace zm {
 
+// Diagnostics on stderr, chosen by the environment variable ZM_LOG (read
+// once): 0 or unset = none, 1 = every failure, 2 = also plan and batch
+// set-up (sizes, resident memory, tuned shapes), 3 = also every call that
+// enqueues device work.  One line per message, "zm: <level>: <text>".
+enum { kLogError = 1, kLogInfo = 2, kLogDebug = 3 };
+int log_level();
+void log_msg(int level, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+
 // Error detail for zm_last_error (thread-local).
 void set_error(const std::string& msg);
 zm_status fail(zm_status s, const std::string& msg);
@@ -147,6 +155,7 @@ hipError_t launch_polar_fft(const zm_plan_s* p, const void* img, long long strid
 hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z,
                           hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s);
+hipError_t launch_count_nonfinite(const zm_plan_s* p, const void* Z, int batch, int* counts, hipStream_t s);
 hipError_t launch_recon_polar(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s);
 hipError_t launch_recon_cart(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s);
 size_t recon_reduce_blocks(const zm_plan_s* p);

@@ -39,6 +39,7 @@ static void check_null_arguments(void) {
     CHECK(zm_workspace_size(NULL, 1, &bytes) == ZM_EINVAL);
     CHECK(zm_moments(NULL, NULL, 1, 0, NULL, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_moments_static(NULL, NULL, 1, 0, NULL, NULL) == ZM_EINVAL);
+    CHECK(zm_count_nonfinite(NULL, NULL, 1, NULL, NULL) == ZM_EINVAL);
     CHECK(zm_spectra(NULL, NULL, 1, 0, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_project(NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_moments_polar(NULL, NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);
