@@ -22,6 +22,10 @@ FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
     # keep the compiler from emitting packed FP32 arithmetic
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a * b + c only within one expression: the same source then rounds
+    # the same way in every kernel that inlines it (standalone, batched and
+    # staged forms give bit-identical moments)
+    "-ffp-contract=on",
     "-I", INCLUDE, "-I", CSRC, "-Wall",
 ]
 

@@ -291,12 +291,10 @@ struct FftLds {
     static constexpr size_t bytes = cplx_count * 2 * sizeof(Real) + (size_t)NTHR * sizeof(float);
 };
 
-// Transform of one ring pair (rings ra, ra + 1) from the 16 samples each
-// thread holds, z[j] = x[t + NT j] with x = f^_ra + i f^_rb: the radix-16
-// pass in registers, the two LDS exchanges through xb (the pair's slot), the
-// pruned last stage, and the split into the two rings' spectra, written to
-// the ring-tile-blocked layout.  Every thread of the workgroup calls it (it
-// holds barriers); vmax collects max |F| for the FP16 split.
+// Transform of one ring pair (rings ra, ra + 1) as a function, for the
+// staged gather; the direct gather includes the same block inline (see
+// fft_pair_body.inc).  Every thread of the workgroup calls it (it holds
+// barriers).
 template <typename Real, int A, int A2, int WG, int TP>
 __device__ __forceinline__ void fft_pair(cplx<Real> (&z)[16], cplx<Real>* xb, const cplx<Real>* tA2,
                                          const cplx<Real>* tLo, const cplx<Real>* tHi, const cplx<Real>* w3, int t,
@@ -306,92 +304,7 @@ __device__ __forceinline__ void fft_pair(cplx<Real> (&z)[16], cplx<Real>* xb, co
     constexpr int NT = L::NT, A1 = L::A1, Q = L::Q, KG = L::KG, S1 = L::S1, S2 = L::S2, NLO = L::NLO;
     const int a1 = t % A1;
     const int q = t / A1;
-    SmallDft<Real, 16>::run(z);
-    // then W_A2^(q k')
-#pragma unroll
-    for (int k = 1; k < 16; ++k) {
-        const C w = tA2[(q * k) % A2];
-        z[k] = mulw(z[k], w.x, w.y);
-    }
-    __syncthreads();  // all reads of the gathered samples are done
-#pragma unroll
-    for (int k = 0; k < 16; ++k) xb[k * S1 + t] = z[k];
-    __syncthreads();
-    // phase 2: for k' in this thread's group, length-Q DFT over q, then W_A^(a1 k2)
-    C y[KG][Q];
-#pragma unroll
-    for (int kk = 0; kk < KG; ++kk) {
-        const int kp = q * KG + kk;
-#pragma unroll
-        for (int qq = 0; qq < Q; ++qq) y[kk][qq] = xb[kp * S1 + a1 + A1 * qq];
-        SmallDft<Real, Q>::run(y[kk]);
-        if constexpr (A1 <= 16) {
-            // W_A^(a1 kp) W_A^(16 a1 k2); A1 divides 16, so the second factor is a W_A2 table entry
-            const int x0 = a1 * kp;  // < 16 A1 <= A
-            const C h = tHi[x0 / NLO], l = tLo[x0 % NLO];
-            const C b = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
-#pragma unroll
-            for (int k2 = 0; k2 < Q; ++k2) {
-                const C u = tA2[a1 * k2 * (16 / A1)];  // 16 a1 k2 / A1 < A2
-                const C w = C{b.x * u.x - b.y * u.y, b.x * u.y + b.y * u.x};
-                y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
-            }
-        } else {
-#pragma unroll
-            for (int k2 = 0; k2 < Q; ++k2) {
-                const int x = a1 * (kp + 16 * k2);  // < A
-                const C h = tHi[x / NLO], l = tLo[x % NLO];
-                const C w = C{h.x * l.x - h.y * l.y, h.x * l.y + h.y * l.x};
-                y[kk][k2] = mulw(y[kk][k2], w.x, w.y);
-            }
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KG; ++kk)
-#pragma unroll
-        for (int k2 = 0; k2 < Q; ++k2) xb[((q * KG + kk) + 16 * k2) * S2 + a1] = y[kk][k2];
-    __syncthreads();
-    // phase 3: bins m (k1 = 0) and A - m (k1 = A1 - 1), then split the two rings
-    const int rt = ra / zm::kRingTile, ri = ra % zm::kRingTile;
-    Real* Fo = Fimg + (size_t)rt * M * 2 * zm::kRingTile + ri;
-    for (int m = t; m < M; m += NT) {
-        C pm = {(Real)0, (Real)0};
-#pragma unroll 4
-        for (int i = 0; i < A1; ++i) pm = pm + xb[m * S2 + i];
-        C nm = pm;
-        if (m > 0) {
-            nm = C{(Real)0, (Real)0};
-            const int row = A2 - m;
-            if constexpr (A1 == 16) {
-                // exp(+2 pi i a1 / 16) as immediates
-                constexpr double c16[16] = {1, kC1, kR2, kS1, 0, -kS1, -kR2, -kC1, -1, -kC1, -kR2, -kS1, 0, kS1, kR2, kC1};
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const C v = xb[row * S2 + i];
-                    const Real wc = (Real)c16[i], ws = (Real)c16[(i + 12) % 16];  // sin = cos(. - pi/2)
-                    nm.x += v.x * wc - v.y * ws;
-                    nm.y += v.x * ws + v.y * wc;
-                }
-            } else {
-#pragma unroll 4
-                for (int i = 0; i < A1; ++i) {
-                    const C v = xb[row * S2 + i];
-                    const C w = w3[i];
-                    nm.x += v.x * w.x - v.y * w.y;
-                    nm.y += v.x * w.y + v.y * w.x;
-                }
-            }
-        }
-        // ring a: (X[m] + conj X[A-m]) / 2 ; ring b: (X[m] - conj X[A-m]) / (2 i)
-        const Real fax = (Real)0.5 * (pm.x + nm.x), fay = (Real)0.5 * (pm.y - nm.y);
-        const Real fbx = (Real)0.5 * (pm.y + nm.y), fby = (Real)0.5 * (nm.x - pm.x);
-        vmax = fmaxf(vmax, fmaxf(fmaxf((float)fabs((double)fax), (float)fabs((double)fay)),
-                                 fmaxf((float)fabs((double)fbx), (float)fabs((double)fby))));
-        Real* o = Fo + (size_t)m * 2 * zm::kRingTile;  // ri even: 2-element aligned
-        *reinterpret_cast<Pair2<Real>*>(o) = Pair2<Real>{fax, fbx};
-        *reinterpret_cast<Pair2<Real>*>(o + zm::kRingTile) = Pair2<Real>{fay, fby};
-    }
+#include "fft_pair_body.inc"
 }
 
 // One workgroup-tile of the fused resample + FFT: rings
@@ -583,7 +496,9 @@ __device__ __forceinline__ void polar_fft_tile(const FftArgs<Real>& g, int img, 
 #pragma unroll
             for (int j = 0; j < 16; ++j) z[j] = xb[t + NT * j];
         }
-        fft_pair<Real, A, A2, WG, TP>(z, xb, tA2, tLo, tHi, w3, t, ra, Fimg, M, vmax);
+        {
+#include "fft_pair_body.inc"
+        }
     }
     if (fmaxbuf != nullptr) {
         red[tid] = vmax;
