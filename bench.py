@@ -75,7 +75,8 @@ METRIC = "4K images/s at N_max=200 (FP32 vs split-BF16) + p50/p99 latency at fix
 # summary; used only while the kernel sources are the ones it was taken on.
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "polar_fft_kernel_4k_n200_b64.md")
 COUNTER_BATCH = 64
-KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_14492_amd", "csrc", f) for f in ("fft_body.h", "polar_fft.hip")]
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2304_14492_amd", "csrc", f)
+                  for f in ("fft_body.h", "fft_pair_body.inc", "polar_fft.hip")]
 
 
 def measured_traffic(batch):
@@ -257,19 +258,8 @@ def batch_form(steps):
         if (side, nmax) not in cache:
             cache[(side, nmax)] = zm.Plan(nmax, side, side, dtype="f32")
         plans.append(cache[(side, nmax)])
-    b = zm.Batch(plans, frames, autotune=True, graph=True)
-    b.run()
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(steps):
-        b.run()
-    e1.record()
-    torch.cuda.synchronize()
-    b.check()
-    ms = e0.elapsed_time(e1) / steps
-    cfg = b.config()
-    b.close()
+    ms, cfg = _time_batch(zm.Batch(plans, frames, autotune=True, graph=True), steps)
+    ms_default, _ = _time_batch(zm.Batch(plans, frames, autotune=False, graph=True), steps)
     # reference: the same frames as one zm_moments launch pair per plan (frames of
     # a plan stacked), back to back on one stream
     groups = {}
@@ -281,6 +271,7 @@ def batch_form(steps):
     for pl, st, ws, z in outs:
         pl.moments(st, out=z, workspace=ws)
     torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(steps):
         for pl, st, ws, z in outs:
@@ -299,11 +290,48 @@ def batch_form(steps):
         nbytes += operand_bytes(pl)
     gbs = nbytes / (ms / 1e3) / 1e9
     return {"images_per_s": round(len(frames) / (ms / 1e3), 1), "ms_per_batch": round(ms, 4), "frames": len(frames),
-            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "queue_items": cfg["n_items"],
+            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "fft_rounds_per_item": cfg["rounds"],
+            "queue_items": cfg["n_items"], "untuned_ms_per_batch": round(ms_default, 4),
             "per_plan_launches_ms": round(ms_plan, 4),
             "roofline": {"bound": "hbm", "kernel": "batch_kernel (persistent: resample + FFT + projection)",
                          "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes}}
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_launch": nbytes},
+            "homogeneous_4k": batch_homogeneous(steps)}
+
+
+def _time_batch(b, steps):
+    """Average time of one graph replay of batch object b (then closed) and its tuned shape."""
+    import torch
+    b.run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        b.run()
+    e1.record()
+    torch.cuda.synchronize()
+    b.check()
+    cfg = b.config()
+    b.close()
+    return e0.elapsed_time(e1) / steps, cfg
+
+
+def batch_homogeneous(steps):
+    """The batched form on 64 benchmark 4K frames of one plan (N_max 200, 1080 x
+    4096 grid): tuned shape and time against the untuned default."""
+    import torch
+    import paper_2304_14492_amd as zm
+    n = 64
+    plan = zm.Plan(NMAX, H, W, dtype="f32", rings=RINGS, angles=ANGLES)
+    base = [torch.from_numpy(f).cuda() for f in make_frames(DISTINCT)]
+    frames = [base[i % DISTINCT].clone() for i in range(n)]
+    ms, cfg = _time_batch(zm.Batch([plan] * n, frames, autotune=True, graph=True), steps)
+    ms_default, cfg_default = _time_batch(zm.Batch([plan] * n, frames, autotune=False, graph=True), steps)
+    return {"frames": n, "ms_per_batch": round(ms, 4), "images_per_s": round(n / (ms / 1e3), 1),
+            "grid": cfg["grid"], "item_order": cfg["order"], "fft_rounds_per_item": cfg["rounds"],
+            "untuned_ms_per_batch": round(ms_default, 4),
+            "untuned": {"grid": cfg_default["grid"], "item_order": cfg_default["order"],
+                        "fft_rounds_per_item": cfg_default["rounds"]}}
 
 
 def reconstruction(reps=3):
@@ -408,7 +436,8 @@ def serving(dtype, count, qps, warmup_s):
         gc.collect()
         gc.disable()  # no collector pauses inside the timed stream
         try:
-            done = serve.run_stream(reqs, sch)
+            # poll while work is queued or in flight; sleep through idle gaps
+            done = serve.run_stream(reqs, sch, idle_sleep=time.sleep)
         finally:
             gc.enable()
         st = serve.latency_stats(done, warmup_s=0.0 if burst else warmup_s, by_size=not burst)

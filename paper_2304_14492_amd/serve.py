@@ -33,6 +33,7 @@ class Request:
     t_done: float = math.nan
     result: object = None
     nbytes: int = 0
+    status: str = "waiting"       # then "done", "timeout" (expired in the queue) or "busy" (queue full)
     # device-side time of the request's launch (seconds; GpuDevice only): the
     # host-to-device copy, the moment computation, the device-to-host copy
     t_h2d: float = math.nan
@@ -49,26 +50,60 @@ class Launch:
     t_launch: float = 0.0
 
 
+class SchedulerBusy(RuntimeError):
+    """The waiting queue is full (the request was not queued)."""
+
+
 class Scheduler:
     """FIFO admission under a byte budget and an in-flight launch cap; admitted
-    requests with the same plan key are launched together (up to max_batch)."""
+    requests with the same plan key are launched together (up to max_batch).
 
-    def __init__(self, device, budget_bytes: int, max_inflight: int = 8, max_batch: int = 16):
+    max_waiting bounds the queue (submit raises SchedulerBusy when it is
+    full); a request that waits longer than timeout_s is dropped with status
+    "timeout" (in `expired`).  set_budget changes the byte budget at run time
+    (down to 0, e.g. while other work holds the memory); requests larger than
+    the budget given at construction are refused at submit."""
+
+    def __init__(self, device, budget_bytes: int, max_inflight: int = 8, max_batch: int = 16,
+                 max_waiting: int | None = None, timeout_s: float | None = None):
         self.dev = device
-        self.budget = int(budget_bytes)
+        self.budget_cap = int(budget_bytes)
+        self.budget = self.budget_cap
         self.max_inflight = max_inflight
         self.max_batch = max_batch
+        self.max_waiting = max_waiting
+        self.timeout_s = timeout_s
         self.waiting = collections.deque()
         self.inflight: list[Launch] = []
         self.used = 0
         self.peak_used = 0
         self.done: list[Request] = []
+        self.expired: list[Request] = []
+
+    def set_budget(self, budget_bytes: int):
+        self.budget = max(0, min(int(budget_bytes), self.budget_cap))
 
     def submit(self, req: Request):
         req.nbytes = self.dev.request_bytes(req)
-        if req.nbytes > self.budget:
+        if req.nbytes > self.budget_cap:
             raise ValueError(f"request {req.rid} needs {req.nbytes} bytes, more than the whole budget")
+        if self.max_waiting is not None and len(self.waiting) >= self.max_waiting:
+            req.status = "busy"
+            raise SchedulerBusy(f"request {req.rid}: {len(self.waiting)} requests already waiting")
         self.waiting.append(req)
+
+    def _expire(self, now: float):
+        if self.timeout_s is None:
+            return
+        keep = collections.deque()
+        for r in self.waiting:
+            if now - r.t_arrival > self.timeout_s:
+                r.status = "timeout"
+                r.t_done = now
+                self.expired.append(r)
+            else:
+                keep.append(r)
+        self.waiting = keep
 
     def _admit(self, now: float):
         # head-of-line FIFO: admit from the front while it fits; gather requests
@@ -95,18 +130,21 @@ class Scheduler:
         return out
 
     def step(self, now: float):
-        """Retire finished launches, then admit and launch what fits."""
+        """Retire finished launches, drop expired requests, then admit and
+        launch what fits."""
         still = []
         for ln in self.inflight:
             if self.dev.is_done(ln):
                 self.dev.finish(ln)
                 for r in ln.reqs:
                     r.t_done = now  # completion observed at this poll
+                    r.status = "done"
                     self.done.append(r)
                 self.used -= ln.nbytes
             else:
                 still.append(ln)
         self.inflight = still
+        self._expire(now)
         if len(self.inflight) < self.max_inflight:
             for ln in self._admit(now):
                 ln.t_launch = now
@@ -117,19 +155,39 @@ class Scheduler:
         return not self.waiting and not self.inflight
 
 
-def run_stream(requests, scheduler: Scheduler, clock=time.perf_counter, sleep=None):
+def run_stream(requests, scheduler: Scheduler, clock=time.perf_counter, sleep=None, idle_sleep=None,
+               rejected=None):
     """Replay `requests` (t_arrival in seconds from the start) through the
     scheduler in real (or fake) time.  Returns the completed requests with
-    t_admit / t_done on the same time axis as t_arrival."""
+    t_admit / t_done on the same time axis as t_arrival.
+
+    The loop polls without pausing while work is queued or in flight (a
+    completion is seen within one poll); `sleep` (no argument) is called
+    after every poll if given.  With nothing queued or in flight,
+    `idle_sleep(seconds)` (e.g. time.sleep) is called until shortly before
+    the next arrival, when that is more than 0.5 ms away.  Requests refused
+    because the queue is full get status "busy" and go to `rejected` (a
+    list) when given, else the SchedulerBusy propagates."""
     pending = collections.deque(sorted(requests, key=lambda r: r.t_arrival))
     start = clock()
     while pending or not scheduler.idle():
         now = clock() - start
         while pending and pending[0].t_arrival <= now:
-            scheduler.submit(pending.popleft())
+            r = pending.popleft()
+            try:
+                scheduler.submit(r)
+            except SchedulerBusy:
+                if rejected is None:
+                    raise
+                r.t_done = now
+                rejected.append(r)
         scheduler.step(now)
         if sleep is not None:
             sleep()
+        if idle_sleep is not None and scheduler.idle() and pending:
+            gap = pending[0].t_arrival - (clock() - start)
+            if gap > 5e-4:
+                idle_sleep(gap - 2e-4)
     return scheduler.done
 
 

@@ -68,3 +68,66 @@ def test_latency_stats():
     st = serve.latency_stats(done)
     assert st["count"] == 100
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["p999_ms"]
+
+
+def test_zero_budget_requests_time_out():
+    # the budget drops to 0 (memory held elsewhere): nothing is admitted, and
+    # every request expires once it has waited timeout_s; restoring the
+    # budget serves later requests normally
+    clock = serve.FakeClock()
+    dev = serve.FakeDevice(clock)
+    sch = serve.Scheduler(dev, budget_bytes=10**9, timeout_s=1e-3)
+    sch.set_budget(0)
+    first = _reqs(10, 1e-5)
+    done = serve.run_stream(first, sch, clock=clock, sleep=lambda: clock.advance(1e-5))
+    assert done == [] and dev.launched == []
+    assert sorted(r.rid for r in sch.expired) == list(range(10))
+    for r in sch.expired:
+        assert r.status == "timeout" and r.result is None
+        assert 1e-3 < r.t_done - r.t_arrival <= 1e-3 + 2e-5
+    sch.set_budget(10**9)
+    later = [serve.Request(rid=100 + i, t_arrival=i * 1e-5, H=48, W=64, nmax=10) for i in range(5)]
+    done = serve.run_stream(later, sch, clock=clock, sleep=lambda: clock.advance(1e-5))
+    assert sorted(r.rid for r in done) == [100 + i for i in range(5)]
+    assert all(r.status == "done" for r in done)
+    assert sch.used == 0
+
+
+def test_full_queue_refuses_with_busy():
+    clock = serve.FakeClock()
+    dev = serve.FakeDevice(clock)
+    sch = serve.Scheduler(dev, budget_bytes=10**9, max_waiting=3)
+    sch.set_budget(0)
+    for i in range(3):
+        sch.submit(serve.Request(rid=i, t_arrival=0.0, H=48, W=64, nmax=10))
+    r = serve.Request(rid=3, t_arrival=0.0, H=48, W=64, nmax=10)
+    with pytest.raises(serve.SchedulerBusy):
+        sch.submit(r)
+    assert r.status == "busy" and len(sch.waiting) == 3
+    # through run_stream the refused requests are collected, the rest served
+    sch.set_budget(10**9)
+    rejected = []
+    burst = [serve.Request(rid=10 + i, t_arrival=0.0, H=48, W=64, nmax=10) for i in range(6)]
+    done = serve.run_stream(burst, sch, clock=clock, sleep=lambda: clock.advance(1e-5), rejected=rejected)
+    assert len(done) + len(rejected) == 9
+    assert all(r.status == "busy" for r in rejected) and len(rejected) >= 1
+    assert sch.used == 0
+
+
+def test_idle_sleep_until_next_arrival():
+    clock = serve.FakeClock()
+    dev = serve.FakeDevice(clock)
+    sch = serve.Scheduler(dev, budget_bytes=10**9)
+    slept = []
+
+    def idle(dt):
+        slept.append(dt)
+        clock.advance(dt)
+
+    reqs = [serve.Request(rid=i, t_arrival=i * 0.01, H=48, W=64, nmax=10) for i in range(5)]
+    done = serve.run_stream(reqs, sch, clock=clock, sleep=lambda: clock.advance(1e-5), idle_sleep=idle)
+    assert len(done) == 5
+    # idle gaps of ~10 ms are slept through (waking 0.2 ms early), never past an arrival
+    assert len(slept) >= 4 and all(0 < dt < 0.01 for dt in slept)
+    for r in done:
+        assert r.t_admit - r.t_arrival <= 2e-5
