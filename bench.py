@@ -290,7 +290,7 @@ def batch_form(steps):
         nbytes += operand_bytes(pl)
     gbs = nbytes / (ms / 1e3) / 1e9
     return {"images_per_s": round(len(frames) / (ms / 1e3), 1), "ms_per_batch": round(ms, 4), "frames": len(frames),
-            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"], "fft_rounds_per_item": cfg["rounds"],
+            "plans": len(cache), "grid": cfg["grid"], "item_order": cfg["order"],
             "queue_items": cfg["n_items"], "untuned_ms_per_batch": round(ms_default, 4),
             "per_plan_launches_ms": round(ms_plan, 4),
             "roofline": {"bound": "hbm", "kernel": "batch_kernel (persistent: resample + FFT + projection)",
@@ -328,10 +328,8 @@ def batch_homogeneous(steps):
     ms, cfg = _time_batch(zm.Batch([plan] * n, frames, autotune=True, graph=True), steps)
     ms_default, cfg_default = _time_batch(zm.Batch([plan] * n, frames, autotune=False, graph=True), steps)
     return {"frames": n, "ms_per_batch": round(ms, 4), "images_per_s": round(n / (ms / 1e3), 1),
-            "grid": cfg["grid"], "item_order": cfg["order"], "fft_rounds_per_item": cfg["rounds"],
-            "untuned_ms_per_batch": round(ms_default, 4),
-            "untuned": {"grid": cfg_default["grid"], "item_order": cfg_default["order"],
-                        "fft_rounds_per_item": cfg_default["rounds"]}}
+            "grid": cfg["grid"], "item_order": cfg["order"], "untuned_ms_per_batch": round(ms_default, 4),
+            "untuned": {"grid": cfg_default["grid"], "item_order": cfg_default["order"]}}
 
 
 def reconstruction(reps=3):

@@ -229,10 +229,10 @@ typedef struct {
 typedef struct zm_batch_s* zm_batch_t; /* owns its queue, descriptors, spectra workspace and graph */
 
 enum {
-    ZM_BATCH_AUTOTUNE = 1, /* time candidate shapes once (persistent grid 1/2/4 x CUs, item order, 1 or 2
-                              FFT rounds per stage-1 item; runs the batch on the given frames); the choice is
-                              cached per batch signature in-process and, if the environment variable
-                              ZM_TUNE_CACHE names a file, in that file */
+    ZM_BATCH_AUTOTUNE = 1, /* time candidate shapes once (persistent grid 1/2/4 x CUs, item order; runs
+                              the batch on the given frames); the choice is cached per batch signature
+                              in-process and, if the environment variable ZM_TUNE_CACHE names a file, in
+                              that file */
     ZM_BATCH_NO_GRAPH = 2  /* launch directly instead of replaying a captured HIP graph */
 };
 
@@ -242,8 +242,7 @@ enum {
  * capture [counter reset + persistent kernel] in a HIP graph.  Synchronous.
  * Each frame's moments are bit-identical to zm_moments on that frame alone,
  * whatever the shape.  Without ZM_BATCH_AUTOTUNE the shape is grid 2 x CUs,
- * costliest tiles first, and the FFT rounds per stage-1 item given by the
- * environment variable ZM_BATCH_ROUNDS ("1" or "2", default 1). */
+ * costliest tiles first. */
 zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out);
 /* Run the batch on `stream` (asynchronous; one graph launch). */
 zm_status zm_batch_run(zm_batch_t batch, zm_stream_t stream);
@@ -257,10 +256,9 @@ zm_status zm_batch_update(zm_batch_t batch, const zm_job* jobs, int njobs);
  * exercises this error path in tests; the kernel still finishes normally). */
 zm_status zm_batch_check(zm_batch_t batch);
 /* Chosen shape: persistent grid size, item order (0 = costliest tiles first,
- * 1 = natural), FFT rounds per stage-1 item (1 or 2; a frame whose padded
- * ring count does not split into the larger items keeps 1), and the queue
- * length and device bytes owned by the batch (any pointer may be NULL). */
-zm_status zm_batch_config(zm_batch_t batch, int* grid, int* order, int* rounds, int* n_items, size_t* device_bytes);
+ * 1 = natural), and the queue length and device bytes owned by the batch
+ * (any pointer may be NULL). */
+zm_status zm_batch_config(zm_batch_t batch, int* grid, int* order, int* n_items, size_t* device_bytes);
 /* Waits for the batch's last run, then frees the batch. */
 zm_status zm_batch_destroy(zm_batch_t batch);
 /* One-shot: create (no graph), run, synchronise, check, destroy. */

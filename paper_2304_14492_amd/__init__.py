@@ -93,8 +93,7 @@ _SIGS = {
     "zm_batch_update": (ctypes.c_int, [_vp, ctypes.POINTER(zm_job), ctypes.c_int]),
     "zm_batch_check": (ctypes.c_int, [_vp]),
     "zm_batch_config": (ctypes.c_int, [_vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(_sz)]),
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(_sz)]),
     "zm_batch_destroy": (ctypes.c_int, [_vp]),
     "zm_moments_batch": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp]),
     "zm_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, ctypes.POINTER(_sz)]),
@@ -535,10 +534,10 @@ class Batch:
         _check(_lib.zm_batch_check(self._h), "zm_batch_check")
 
     def config(self):
-        g, o, r, n, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), _sz()
-        _check(_lib.zm_batch_config(self._h, ctypes.byref(g), ctypes.byref(o), ctypes.byref(r), ctypes.byref(n),
-                                    ctypes.byref(b)), "zm_batch_config")
-        return dict(grid=g.value, order=o.value, rounds=r.value, n_items=n.value, device_bytes=b.value)
+        g, o, n, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), _sz()
+        _check(_lib.zm_batch_config(self._h, ctypes.byref(g), ctypes.byref(o), ctypes.byref(n), ctypes.byref(b)),
+               "zm_batch_config")
+        return dict(grid=g.value, order=o.value, n_items=n.value, device_bytes=b.value)
 
     def close(self):
         if getattr(self, "_h", None):

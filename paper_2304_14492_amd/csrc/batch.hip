@@ -53,15 +53,10 @@ constexpr bool batch_variant_ok() {
     return A2 * 2 <= A && FftLds<float, A, A2>::bytes <= 80 * 1024;  // two workgroups per CU
 }
 
-// A stage-1 item covers RI rounds of the FFT body (RI x P ring pairs of one
-// frame, P the pairs one round of the 512-thread body transforms): RI = 1 is
-// the standalone kernel's tile; the autotuner also tries RI = 2 (fewer, larger
-// items: fewer queue claims, fewer radial neighbours in flight per XCD).
-constexpr int kMaxRounds = 2;
-template <int A, int RI>
-constexpr int tile_pairs_arg() {
-    return RI == 1 ? 1 : RI * FftShape<float, A, 512, 1>::P;
-}
+// A stage-1 item is one round of the FFT body: the standalone kernel's tile
+// (P ring pairs of one frame, P the pairs the 512-thread body transforms at
+// once).
+constexpr int kItemPairs = 1;
 
 template <int AI, int A2I>
 constexpr size_t lds_of() {
@@ -84,7 +79,7 @@ static_assert(kProjUnits * chunk_lds_bytes<ZM_F32>() <= kBatchLds, "stage-2 part
 
 struct BatchJob {
     FftArgs<float> fa;
-    int variant;  // (RI - 1) * 20 + AI * 5 + A2I
+    int variant;  // AI * 5 + A2I
     int group;
 };
 
@@ -157,7 +152,7 @@ struct Claim {
 
 // Runs one stage-1 tile; thread 0 claims the next item of `c`'s range on the
 // way and returns it (-1 on other threads or when the range is exhausted).
-template <int AI, int A2I, int RI>
+template <int AI, int A2I>
 __device__ __attribute__((noinline)) int run_tile(const BatchJob* j, int tile, Claim c) {
     unsigned k = 0xffffffffu;
     if (threadIdx.x == 0) k = atomicAdd(c.head, 1u);
@@ -170,31 +165,29 @@ __device__ __attribute__((noinline)) int run_tile(const BatchJob* j, int tile, C
         fa.F = global_field(&j->fa.F);
         fa.fmaxbuf = global_field(&j->fa.fmaxbuf);
         tile = __builtin_amdgcn_readfirstlane(tile);
-        polar_fft_tile<float, kAList[AI], kA2List[A2I], 512, tile_pairs_arg<kAList[AI], RI>()>(fa, 0, tile,
-                                                                                              g_batch_smem);
+        polar_fft_tile<float, kAList[AI], kA2List[A2I], 512, kItemPairs>(fa, 0, tile, g_batch_smem);
     }
     return k < (unsigned)c.len ? c.off + (int)k : -1;
 }
 
-template <int AI, int RI>
+template <int AI>
 __device__ __forceinline__ int run_tile_a2(const BatchJob* j, int a2i, int tile, Claim c) {
     switch (a2i) {
-        case 0: return run_tile<AI, 0, RI>(j, tile, c);
-        case 1: return run_tile<AI, 1, RI>(j, tile, c);
-        case 2: return run_tile<AI, 2, RI>(j, tile, c);
-        case 3: return run_tile<AI, 3, RI>(j, tile, c);
-        case 4: return run_tile<AI, 4, RI>(j, tile, c);
+        case 0: return run_tile<AI, 0>(j, tile, c);
+        case 1: return run_tile<AI, 1>(j, tile, c);
+        case 2: return run_tile<AI, 2>(j, tile, c);
+        case 3: return run_tile<AI, 3>(j, tile, c);
+        case 4: return run_tile<AI, 4>(j, tile, c);
         default: return -1;
     }
 }
 
-template <int RI>
 __device__ __forceinline__ int run_tile_a(const BatchJob* j, int ai, int a2i, int tile, Claim c) {
     switch (ai) {
-        case 0: return run_tile_a2<0, RI>(j, a2i, tile, c);
-        case 1: return run_tile_a2<1, RI>(j, a2i, tile, c);
-        case 2: return run_tile_a2<2, RI>(j, a2i, tile, c);
-        case 3: return run_tile_a2<3, RI>(j, a2i, tile, c);
+        case 0: return run_tile_a2<0>(j, a2i, tile, c);
+        case 1: return run_tile_a2<1>(j, a2i, tile, c);
+        case 2: return run_tile_a2<2>(j, a2i, tile, c);
+        case 3: return run_tile_a2<3>(j, a2i, tile, c);
         default: return -1;
     }
 }
@@ -307,9 +300,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
             if (tid == 0 && pend && it.group != pend_group) release();
             const BatchJob* j = jobs + it.idx;
             const int variant = j->variant;
-            const int ri = variant / 20, ai = (variant % 20) / 5, a2i = variant % 5;
-            const int claimed = ri == 0 ? run_tile_a<1>(j, ai, a2i, it.sub, claim)
-                                        : run_tile_a<2>(j, ai, a2i, it.sub, claim);
+            const int claimed = run_tile_a(j, variant / 5, variant % 5, it.sub, claim);
             // this wave's spectra stores have completed before the barriers
             // that precede thread 0's release
             __builtin_amdgcn_s_waitcnt(0);
@@ -385,17 +376,15 @@ bool variant_ok(int ai, int a2i) {
         {host_ok<3, 0>(), host_ok<3, 1>(), host_ok<3, 2>(), host_ok<3, 3>(), host_ok<3, 4>()}};
     return ai >= 0 && a2i >= 0 && tab[ai][a2i];
 }
-// ring pairs per stage-1 item of RI rounds: FftShape<float, A, 512, tile_pairs_arg<A, RI>()>::PAIRS
-template <int RI>
-int pairs_of_ri(int A) {
+// ring pairs per stage-1 item
+int pairs_of(int A) {
     switch (A) {
-        case 512: return FftShape<float, 512, 512, tile_pairs_arg<512, RI>()>::PAIRS;
-        case 1024: return FftShape<float, 1024, 512, tile_pairs_arg<1024, RI>()>::PAIRS;
-        case 2048: return FftShape<float, 2048, 512, tile_pairs_arg<2048, RI>()>::PAIRS;
-        default: return FftShape<float, 4096, 512, tile_pairs_arg<4096, RI>()>::PAIRS;
+        case 512: return FftShape<float, 512, 512, kItemPairs>::PAIRS;
+        case 1024: return FftShape<float, 1024, 512, kItemPairs>::PAIRS;
+        case 2048: return FftShape<float, 2048, 512, kItemPairs>::PAIRS;
+        default: return FftShape<float, 4096, 512, kItemPairs>::PAIRS;
     }
 }
-int pairs_of(int A, int ri) { return ri == 2 ? pairs_of_ri<2>(A) : pairs_of_ri<1>(A); }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
@@ -417,8 +406,6 @@ struct zm_batch_s {
     QueueInfo qinfo{};
     int grid = 0;
     int order = 0;  // 0: cost-descending stage 1, 1: natural
-    int rounds = 1; // rounds of the FFT body per stage-1 item (jobs whose rings do not divide evenly keep 1)
-    std::vector<int> job_rounds;  // per job
     // device memory: one block, laid out by batch_layout
     size_t o_items = 0, o_jobs = 0, o_groups = 0, o_zptr = 0, o_zero = 0;
     std::vector<size_t> foff;  // spectra of each group
@@ -442,8 +429,6 @@ struct zm_batch_s {
 
 namespace {
 
-void set_rounds(zm_batch_s* b, int rounds);
-
 // Copies the queue (in the current item order), descriptors and output
 // pointers to the device, asynchronously on `s`; the host copies stay in the
 // batch until the caller has synchronised `s`.
@@ -453,14 +438,13 @@ zm_status upload(zm_batch_s* b, hipStream_t s) {
         std::stable_sort(s1.begin(), s1.end(), [&](const BatchItem& x, const BatchItem& y) {
             const zm_plan_s* px = b->plans[x.idx];
             const zm_plan_s* py = b->plans[y.idx];
-            return (long)px->A * pairs_of(px->A, b->job_rounds[x.idx]) >
-                   (long)py->A * pairs_of(py->A, b->job_rounds[y.idx]);
+            return (long)px->A * pairs_of(px->A) > (long)py->A * pairs_of(py->A);
         });
     }
     // split stage 1 into kQueues contiguous ranges of about equal cost (samples per item)
     auto cost = [&](const BatchItem& x) {
         const zm_plan_s* px = b->plans[x.idx];
-        return (double)px->A * pairs_of(px->A, b->job_rounds[x.idx]);
+        return (double)px->A * pairs_of(px->A);
     };
     double total = 0.0;
     for (const BatchItem& x : s1) total += cost(x);
@@ -540,9 +524,9 @@ std::string signature(const zm_batch_s* b) {
     return sig;
 }
 
-// A tuned shape: persistent grid, stage-1 item order, FFT rounds per stage-1 item.
+// A tuned shape: persistent grid, stage-1 item order.
 struct TunedShape {
-    int grid, order, rounds;
+    int grid, order;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TunedShape> g_tune;  // batch signature -> shape
@@ -557,13 +541,12 @@ void tune_cache_load() {
     if (!f) return;
     char line[8192];
     while (std::fgets(line, sizeof line, f)) {
-        // one entry per line: <grid> <order> <rounds> <signature>
-        int grid = 0, order = 0, rounds = 0, n = 0;
-        if (std::sscanf(line, "%d %d %d %n", &grid, &order, &rounds, &n) == 3 && grid > 0 && rounds >= 1 &&
-            rounds <= kMaxRounds) {
+        // one entry per line: <grid> <order> <signature>
+        int grid = 0, order = 0, n = 0;
+        if (std::sscanf(line, "%d %d %n", &grid, &order, &n) == 2 && grid > 0 && (order == 0 || order == 1)) {
             std::string sig(line + n);
             while (!sig.empty() && (sig.back() == '\n' || sig.back() == '\r')) sig.pop_back();
-            g_tune[sig] = TunedShape{grid, order, rounds};
+            g_tune[sig] = TunedShape{grid, order};
         }
     }
     std::fclose(f);
@@ -575,7 +558,7 @@ void tune_cache_store(const std::string& sig, const TunedShape& t) {
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %d %s\n", t.grid, t.order, t.rounds, sig.c_str());
+    std::fprintf(f, "%d %d %s\n", t.grid, t.order, sig.c_str());
     std::fclose(f);
 }
 
@@ -600,38 +583,34 @@ zm_status autotune(zm_batch_s* b, int cus) {
     if (it != g_tune.end()) {
         b->grid = it->second.grid;
         b->order = it->second.order;
-        set_rounds(b, it->second.rounds);
         return upload_sync(b);
     }
     hipEvent_t e0, e1;
     ZM_HIP(hipEventCreate(&e0));
     ZM_HIP(hipEventCreate(&e1));
     float best = 1e30f;
-    TunedShape bt{2 * cus, 0, 1};
+    TunedShape bt{2 * cus, 0};
     const int grids[3] = {cus, 2 * cus, 4 * cus};
-    for (int rounds = 1; rounds <= kMaxRounds; ++rounds) {
-        set_rounds(b, rounds);
-        for (int order = 0; order < 2; ++order) {
-            b->order = order;
-            zm_status st = upload_sync(b);
-            if (st != ZM_OK) return st;
-            for (int gi = 0; gi < 3; ++gi) {
-                b->grid = grids[gi];
-                float ms_best = 1e30f;
-                for (int rep = 0; rep < 3; ++rep) {
-                    ZM_HIP(hipEventRecord(e0, b->stream));
-                    hipError_t e = enqueue(b, b->stream);
-                    if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
-                    ZM_HIP(hipEventRecord(e1, b->stream));
-                    ZM_HIP(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    ZM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    if (rep > 0) ms_best = std::min(ms_best, ms);
-                }
-                if (ms_best < best) {
-                    best = ms_best;
-                    bt = TunedShape{grids[gi], order, rounds};
-                }
+    for (int order = 0; order < 2; ++order) {
+        b->order = order;
+        zm_status st = upload_sync(b);
+        if (st != ZM_OK) return st;
+        for (int gi = 0; gi < 3; ++gi) {
+            b->grid = grids[gi];
+            float ms_best = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                ZM_HIP(hipEventRecord(e0, b->stream));
+                hipError_t e = enqueue(b, b->stream);
+                if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
+                ZM_HIP(hipEventRecord(e1, b->stream));
+                ZM_HIP(hipEventSynchronize(e1));
+                float ms = 0.f;
+                ZM_HIP(hipEventElapsedTime(&ms, e0, e1));
+                if (rep > 0) ms_best = std::min(ms_best, ms);
+            }
+            if (ms_best < best) {
+                best = ms_best;
+                bt = TunedShape{grids[gi], order};
             }
         }
     }
@@ -641,7 +620,6 @@ zm_status autotune(zm_batch_s* b, int cus) {
     if (st != ZM_OK) return st;
     b->grid = bt.grid;
     b->order = bt.order;
-    set_rounds(b, bt.rounds);
     tune_cache_store(sig, bt);
     return upload_sync(b);
 }
@@ -670,23 +648,16 @@ zm_status fill_pointers(zm_batch_s* b, const zm_job* jobs) {
     return ZM_OK;
 }
 
-// Stage-1 items for `rounds` FFT rounds per item: a job whose padded ring
-// count is not a multiple of the larger item keeps one round per item (an
-// item never reaches past the job's rings).  Sets the jobs' variants and the
-// groups' tile counts (what a stage-2 item waits for).
-void set_rounds(zm_batch_s* b, int rounds) {
-    b->rounds = rounds;
-    b->job_rounds.assign(b->njobs, 1);
+// Stage-1 items, the jobs' variants and the groups' tile counts (what a
+// stage-2 item waits for).
+void build_stage1(zm_batch_s* b) {
     b->stage1.clear();
     for (auto& G : b->hgroups) G.tiles_total = 0;
     for (int i = 0; i < b->njobs; ++i) {
         const zm_plan_s* p = b->plans[i];
-        int ri = rounds;
-        if (p->Rp % (2 * pairs_of(p->A, ri)) != 0) ri = 1;
-        b->job_rounds[i] = ri;
         BatchJob& j = b->hjobs[i];
-        j.variant = (ri - 1) * 20 + a_index(p->A) * 5 + a2_index(p->A2);
-        const int tiles = p->Rp / (2 * pairs_of(p->A, ri));
+        j.variant = a_index(p->A) * 5 + a2_index(p->A2);
+        const int tiles = p->Rp / (2 * pairs_of(p->A));
         for (int t = 0; t < tiles; ++t) b->stage1.push_back(BatchItem{0, i, t, j.group});
         b->hgroups[j.group].tiles_total += (unsigned)tiles;
     }
@@ -733,7 +704,7 @@ zm_status batch_layout(zm_batch_s* b, const zm_job* jobs, int njobs) {
     }
     b->n_zero = kCtrGroups + b->ngroups + 1 + njobs;  // heads, group counters, error flag, F16 max per frame
     size_t n_items_max = 0;
-    for (int i = 0; i < njobs; ++i) n_items_max += (size_t)b->plans[i]->Rp / (2 * pairs_of(b->plans[i]->A, 1));
+    for (int i = 0; i < njobs; ++i) n_items_max += (size_t)b->plans[i]->Rp / (2 * pairs_of(b->plans[i]->A));
     for (int g = 0; g < b->ngroups; ++g) {
         const zm_plan_s* p = b->plans[members[g][0]];
         const size_t units = p->items.size() * ((2 * members[g].size() + 31) / 32);
@@ -800,7 +771,7 @@ zm_status batch_layout(zm_batch_s* b, const zm_job* jobs, int njobs) {
         const int blocks = (G.pa.n_units + kProjUnits - 1) / kProjUnits;
         for (int k = 0; k < blocks; ++k) b->stage2.push_back(BatchItem{1, g, k, -1});
     }
-    set_rounds(b, 1);
+    build_stage1(b);
     return fill_pointers(b, jobs);
 }
 
@@ -866,10 +837,6 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
     const int cus = device_cus(b->device);
     b->grid = 2 * cus;
     b->order = 0;
-    if (const char* r = std::getenv("ZM_BATCH_ROUNDS")) {
-        // FFT rounds per stage-1 item without autotuning (1 or 2)
-        if (r[0] >= '1' && r[0] <= '0' + kMaxRounds && r[1] == '\0') set_rounds(b, r[0] - '0');
-    }
     e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -883,9 +850,9 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         destroy_batch(b);
         return st;
     }
-    log_msg(kLogInfo, "batch %p: %d jobs, %d queue items, %zu device bytes; grid %d, item order %d, %d FFT round(s) "
-        "per item%s%s", (void*)b, njobs, b->n_items, b->d_bytes, b->grid, b->order, b->rounds,
-        (flags & ZM_BATCH_AUTOTUNE) ? " (tuned)" : "", (flags & ZM_BATCH_NO_GRAPH) ? "" : ", graph captured");
+    log_msg(kLogInfo, "batch %p: %d jobs, %d queue items, %zu device bytes; grid %d, item order %d%s%s", (void*)b,
+            njobs, b->n_items, b->d_bytes, b->grid, b->order, (flags & ZM_BATCH_AUTOTUNE) ? " (tuned)" : "",
+            (flags & ZM_BATCH_NO_GRAPH) ? "" : ", graph captured");
     *out = b;
     return ZM_OK;
 }
@@ -926,11 +893,10 @@ zm_status zm_batch_check(zm_batch_t b) {
     return check_error_flag(b, b->stream);
 }
 
-zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* rounds, int* n_items, size_t* device_bytes) {
+zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* n_items, size_t* device_bytes) {
     if (!b) return fail(ZM_EINVAL, "null batch");
     if (grid) *grid = b->grid;
     if (order) *order = b->order;
-    if (rounds) *rounds = b->rounds;
     if (n_items) *n_items = b->n_items;
     if (device_bytes) *device_bytes = b->d_bytes;
     return ZM_OK;

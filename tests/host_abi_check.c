@@ -47,7 +47,7 @@ static void check_null_arguments(void) {
     CHECK(zm_batch_run(NULL, NULL) == ZM_EINVAL);
     CHECK(zm_batch_update(NULL, NULL, 0) == ZM_EINVAL);
     CHECK(zm_batch_check(NULL) == ZM_EINVAL);
-    CHECK(zm_batch_config(NULL, NULL, NULL, NULL, NULL, NULL) == ZM_EINVAL);
+    CHECK(zm_batch_config(NULL, NULL, NULL, NULL, NULL) == ZM_EINVAL);
     CHECK(zm_batch_destroy(NULL) == ZM_EINVAL);
     CHECK(zm_moments_batch(NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_batch_workspace_size(NULL, 0, &bytes) == ZM_EINVAL);

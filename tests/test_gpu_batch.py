@@ -212,23 +212,3 @@ def test_destroy_reports_busy(zm):
     assert torch.equal(b.outs[0], ref[0])
     plan.close()
     assert plan.handle is None
-
-
-@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
-def test_two_rounds_per_item_bit_exact(zm, dtype, monkeypatch):
-    # stage-1 items of two FFT rounds (ZM_BATCH_ROUNDS=2); frames whose padded
-    # ring count does not split into such items keep one round per item
-    monkeypatch.setenv("ZM_BATCH_ROUNDS", "2")
-    specs = [(256, 30, 21), (384, 50, 22), (512, 100, 23), (768, 30, 24), (1024, 50, 25), (2048, 100, 26),
-             (300, 30, 27)]
-    frames = _frames(specs)
-    plans = _plans(zm, specs, dtype)
-    b = zm.Batch(plans, frames, graph=True)
-    assert b.config()["rounds"] == 2
-    b.run()
-    b.check()
-    ref = [p.moments(f) for p, f in zip(plans, frames)]
-    torch.cuda.synchronize()
-    for z, r in zip(b.outs, ref):
-        assert torch.equal(z, r)
-    b.close()
