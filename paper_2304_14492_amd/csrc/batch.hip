@@ -90,7 +90,7 @@ struct BatchGroup {
 };
 
 struct BatchItem {
-    int kind;  // 0: stage-1 (job, tile), 1: stage-2 (group, block of 8 units)
+    int kind;  // 0: stage-1 (job, tile), 1: stage-2 (group, kProjUnits output blocks)
     int idx;
     int sub;
     int group;  // stage-1: the job's plan group; stage-2: -1
@@ -257,14 +257,15 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
     const int tid = threadIdx.x;
     // workgroups are dealt round-robin to the XCDs
     const int home = (int)(blockIdx.x % kQueues);
-    // Thread 0 holds the next item (claimed during the current one) and the
-    // workgroup's finished tiles that are not yet released (`pend` tiles of
-    // group `pend_group`).  A release writes the XCD's L2 back, which stalls
-    // the gathers of every workgroup on that XCD, so it is done once per run
-    // of tiles of one group: before a tile of another group, before a
-    // stage-2 item (which may wait) and before the exit.  No stage-2 item is
-    // popped while stage-1 items remain, and a workgroup releases before it
-    // runs one, so every wait still ends.
+    // Thread 0 holds the next item (claimed during the current one).  Every
+    // thread tracks the workgroup's finished tiles that are not yet released
+    // (`pend` tiles of group `pend_group`; the same in all threads).  A
+    // release writes the XCD's L2 back, which stalls the gathers of every
+    // workgroup on that XCD, so it is done once per run of tiles of one
+    // group: before a tile of another group, before a stage-2 item (which may
+    // wait) and before the exit; the waves wait for their stores only then.
+    // No stage-2 item is popped while stage-1 items remain, and a workgroup
+    // releases before it runs one, so every wait still ends.
     int next = 0, pend_group = -1;
     unsigned pend = 0;
     // Thread 0 also remembers what its last acquire covered: the group it
@@ -291,31 +292,27 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(4
         if (tid == 0) cur = next;
         __syncthreads();
         const int i = __builtin_amdgcn_readfirstlane(cur);  // uniform: scalar loads of the item and its job
-        if (i < 0) {
-            if (tid == 0 && pend) release();
-            return;
+        const BatchItem it = i >= 0 ? items[i] : BatchItem{-1, -1, 0, -1};
+        if (pend && (it.kind != 0 || it.group != pend_group)) {
+            // every wave's stores of the pending tiles have completed before
+            // the barrier that precedes thread 0's release
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+            if (tid == 0) release();
+            pend = 0;
         }
-        const BatchItem it = items[i];
+        if (i < 0) return;
         if (it.kind == 0) {
-            if (tid == 0 && pend && it.group != pend_group) release();
             const BatchJob* j = jobs + it.idx;
             const int variant = j->variant;
             const int claimed = run_tile_a(j, variant / 5, variant % 5, it.sub, claim);
-            // this wave's spectra stores have completed before the barriers
-            // that precede thread 0's release
-            __builtin_amdgcn_s_waitcnt(0);
-            if (tid == 0) {
-                pend_group = it.group;
-                ++pend;
-                next = claimed >= 0 ? claimed : pop_item(q, ctr, home, true);
-            }
+            pend_group = it.group;
+            ++pend;
+            if (tid == 0) next = claimed >= 0 ? claimed : pop_item(q, ctr, home, true);
         } else {
             const BatchGroup* g = groups + it.idx;
             const unsigned need = g->tiles_total;
-            if (tid == 0) {
-                if (pend) release();
-                next = pop_item(q, ctr, home, true);
-            }
+            if (tid == 0) next = pop_item(q, ctr, home, true);
             if (tid == 0 && !acq_all && it.idx != acq_group) {
                 unsigned spins = 0;
                 while (__hip_atomic_load(&ctr[kCtrGroups + it.idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
