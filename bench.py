@@ -420,7 +420,9 @@ def dedup_throughput(side=256, n_distinct=700, reps=3):
 def serving(dtype, count, qps, warmup_s):
     """Serving form for one projection dtype: saturation throughput (every
     request queued at t = 0), then Poisson streams at the fixed rate `qps` and
-    at 50 % / 80 % of the measured saturation."""
+    at 50 % / 80 % of the measured saturation, one zm_moments launch per plan
+    group; then (`persistent`) saturation and the fixed rate with all admitted
+    requests of a round in one persistent launch."""
     from paper_2304_14492_amd import serve
     dev = serve.GpuDevice(dtype=dtype, n_streams=4)
 
@@ -447,6 +449,10 @@ def serving(dtype, count, qps, warmup_s):
     for rate in (qps, 0.5 * sat, 0.8 * sat):
         n = int(min(count, max(200, rate * (warmup_s + 8.0))))  # about 8 s after the warm-up
         out["runs"].append(one(rate, n))
+    dev = serve.GpuDevice(dtype=dtype, n_streams=4, mode="persistent")
+    sat_p = one(qps, max(count // 4, 200), burst=True)["images_per_s"]
+    out["persistent"] = {"saturation_images_per_s": sat_p,
+                         "runs": [one(qps, int(min(count, max(200, qps * (warmup_s + 8.0)))))]}
 
     def rnd(v):
         if isinstance(v, float):

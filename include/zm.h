@@ -274,6 +274,23 @@ zm_status zm_moments_batch(const zm_job* jobs, int njobs, zm_stream_t stream);
  * ZM_EUNSUPPORTED (a plan outside the batched form), ZM_EDEVICE. */
 zm_status zm_batch_workspace_size(const zm_job* jobs, int njobs, size_t* bytes);
 zm_status zm_moments_batch_ws(const zm_job* jobs, int njobs, void* d_ws, size_t ws_bytes, zm_stream_t stream);
+/* The one-shot batch without any wait, for request loops that keep several
+ * launches in flight: as zm_moments_batch_ws (same d_ws layout and size),
+ * but the queue and descriptors go through h_stage, caller-owned pinned
+ * host memory (hipHostMalloc or equivalent, 16-byte aligned) of
+ * zm_batch_stage_size() bytes: the call writes them there, enqueues one
+ * host-to-device copy, the persistent launch and a copy of the run's error
+ * flag back into h_stage on `stream`, and returns.  d_ws and h_stage must
+ * stay untouched until `stream` has passed the work; then
+ * zm_batch_stage_status(h_stage) returns ZM_EDEVICE if a projection item
+ * waited past its bound (ZM_OK otherwise).  Each plan records the work's
+ * completion on `stream` (zm_destroy reports ZM_EBUSY until then).  It
+ * allocates no device memory.  Errors: as zm_moments_batch_ws, plus
+ * ZM_EINVAL for a null, misaligned or too small staging buffer. */
+zm_status zm_batch_stage_size(const zm_job* jobs, int njobs, size_t* bytes);
+zm_status zm_moments_batch_async(const zm_job* jobs, int njobs, void* d_ws, size_t ws_bytes, void* h_stage,
+                                 size_t stage_bytes, zm_stream_t stream);
+zm_status zm_batch_stage_status(const void* h_stage);
 
 /* ---- Reconstruction (Sec. 2.2 eq. (9)), error (Sec. 2.4 eq. (13)), min-max ---- */
 

@@ -98,6 +98,9 @@ _SIGS = {
     "zm_moments_batch": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp]),
     "zm_batch_workspace_size": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, ctypes.POINTER(_sz)]),
     "zm_moments_batch_ws": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp, _sz, _vp]),
+    "zm_batch_stage_size": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, ctypes.POINTER(_sz)]),
+    "zm_moments_batch_async": (ctypes.c_int, [ctypes.POINTER(zm_job), ctypes.c_int, _vp, _sz, _vp, _sz, _vp]),
+    "zm_batch_stage_status": (ctypes.c_int, [_vp]),
     "zm_cartesian_workspace_size": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.POINTER(_sz)]),
     "zm_moment_cartesian": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_longlong, ctypes.c_int,
                                            ctypes.c_int, ctypes.c_int, _vp, _vp, _sz, _vp]),
@@ -577,6 +580,42 @@ def moments_batch(plans, frames, outs=None, workspace=None, stream=None):
     _check(_lib.zm_moments_batch_ws(jobs, len(jobs), _vp(workspace.data_ptr()), workspace.numel(),
                                     _stream_handle(stream)), "zm_moments_batch_ws")
     return outs
+
+
+class BatchLaunch:
+    """zm_moments_batch_async: one persistent launch of a mixed batch,
+    enqueued on ``stream`` without waiting.  Allocates (unless given) the
+    device workspace and a pinned staging buffer and keeps them, the frames
+    and the outputs referenced until ``check`` has run after the stream
+    passed the launch (e.g. after ``done.synchronize()`` or ``done.query()``
+    of an event recorded after it)."""
+
+    def __init__(self, plans, frames, outs=None, workspace=None, stage=None, stream=None):
+        import torch
+        if outs is None:
+            outs = [torch.empty(p.num_moments, 2, dtype=p._real_dtype(), device=f.device)
+                    for p, f in zip(plans, frames)]
+        jobs = _jobs(plans, frames, outs)
+        n, m = _sz(), _sz()
+        _check(_lib.zm_batch_workspace_size(jobs, len(jobs), ctypes.byref(n)), "zm_batch_workspace_size")
+        _check(_lib.zm_batch_stage_size(jobs, len(jobs), ctypes.byref(m)), "zm_batch_stage_size")
+        if workspace is None:
+            workspace = torch.empty(n.value, dtype=torch.uint8, device=frames[0].device)
+        if stage is None:
+            stage = torch.empty(m.value, dtype=torch.uint8, pin_memory=True)
+        _need(workspace, "workspace", dtype=torch.uint8, min_numel=n.value, device=plans[0].device)
+        _need(stage, "stage", dtype=torch.uint8, min_numel=m.value, on_device=False)
+        if stage.is_cuda or not stage.is_pinned():
+            raise ValueError("stage: must be pinned host memory")
+        _keep_alive(stream, workspace, *frames, *outs)
+        self.plans, self.frames, self.outs, self.workspace, self.stage = plans, frames, outs, workspace, stage
+        _check(_lib.zm_moments_batch_async(jobs, len(jobs), _vp(workspace.data_ptr()), workspace.numel(),
+                                           _vp(stage.data_ptr()), stage.numel(), _stream_handle(stream)),
+               "zm_moments_batch_async")
+
+    def check(self):
+        """The run's status from the staging buffer (call after the stream passed it)."""
+        _check(_lib.zm_batch_stage_status(_vp(self.stage.data_ptr())), "zm_batch_stage_status")
 
 
 def as_complex(Z):

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -429,7 +430,9 @@ namespace {
 // Copies the queue (in the current item order), descriptors and output
 // pointers to the device, asynchronously on `s`; the host copies stay in the
 // batch until the caller has synchronised `s`.
-zm_status upload(zm_batch_s* b, hipStream_t s) {
+// Orders the queue (current item order, stage 1 split into the per-XCD
+// ranges) into b->hitems and the output pointers into b->hzptrs.
+void prepare_queue(zm_batch_s* b) {
     std::vector<BatchItem> s1 = b->stage1;
     if (b->order == 0) {
         std::stable_sort(s1.begin(), s1.end(), [&](const BatchItem& x, const BatchItem& y) {
@@ -461,6 +464,10 @@ zm_status upload(zm_batch_s* b, hipStream_t s) {
     b->n_items = (int)b->hitems.size();
     b->hzptrs.clear();
     for (auto& v : b->zptrs) b->hzptrs.insert(b->hzptrs.end(), v.begin(), v.end());
+}
+
+zm_status upload(zm_batch_s* b, hipStream_t s) {
+    prepare_queue(b);
     ZM_HIP(hipMemcpyAsync(b->d_items, b->hitems.data(), b->hitems.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
     ZM_HIP(hipMemcpyAsync(b->d_jobs, b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, s));
     ZM_HIP(hipMemcpyAsync(b->d_groups, b->hgroups.data(), b->hgroups.size() * sizeof(BatchGroup),
@@ -964,6 +971,83 @@ zm_status zm_moments_batch_ws(const zm_job* jobs, int njobs, void* d_ws, size_t 
     if (st == ZM_OK) st = check_error_flag(b, s);
     destroy_batch(b);
     return st;
+}
+
+// Staging buffer of the asynchronous one-shot: a header, then an image of
+// the device block's [o_items, o_zero) range (queue, descriptors, output
+// pointers) copied to the device in one transfer.
+namespace {
+constexpr unsigned kStageMagic = 0x7a6d5354u;  // "zmST"
+constexpr size_t kStageHeader = 256;
+struct StageHeader {
+    unsigned magic;
+    unsigned flag;  // the run's error flag, copied back at the end of the enqueued work
+};
+}  // namespace
+
+zm_status zm_batch_stage_size(const zm_job* jobs, int njobs, size_t* bytes) {
+    if (!jobs || !bytes || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list and an output pointer");
+    zm_batch_s b;
+    zm_status st = batch_layout(&b, jobs, njobs);
+    if (st != ZM_OK) return st;
+    *bytes = kStageHeader + (b.o_zero - b.o_items);
+    return ZM_OK;
+}
+
+zm_status zm_moments_batch_async(const zm_job* jobs, int njobs, void* d_ws, size_t ws_bytes, void* h_stage,
+                                 size_t stage_bytes, zm_stream_t stream) {
+    if (!jobs || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list");
+    if (!d_ws || !h_stage) return fail(ZM_EINVAL, "null workspace or staging buffer");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(ZM_EINVAL, "workspace must be 256-byte aligned");
+    if (((uintptr_t)h_stage & 15) != 0) return fail(ZM_EINVAL, "staging buffer must be 16-byte aligned");
+    zm_batch_s* b = new zm_batch_s();
+    zm_status st = batch_layout(b, jobs, njobs);
+    if (st == ZM_OK && ws_bytes < b->d_bytes)
+        st = fail(ZM_EINVAL, "workspace too small: need " + std::to_string(b->d_bytes) + " bytes");
+    const size_t need = kStageHeader + (b->o_zero - b->o_items);
+    if (st == ZM_OK && stage_bytes < need)
+        st = fail(ZM_EINVAL, "staging buffer too small: need " + std::to_string(need) + " bytes");
+    if (st != ZM_OK) {
+        destroy_batch(b);
+        return st;
+    }
+    zm::DeviceGuard guard(b->device);
+    if (guard.err != hipSuccess) {
+        destroy_batch(b);
+        return hip_fail(guard.err, "hipSetDevice");
+    }
+    batch_bind(b, (char*)d_ws);
+    b->grid = 2 * device_cus(b->device);
+    prepare_queue(b);
+    char* img = (char*)h_stage + kStageHeader;  // mirrors d_ws + o_items
+    std::memcpy(img, b->hitems.data(), b->hitems.size() * sizeof(BatchItem));
+    std::memcpy(img + (b->o_jobs - b->o_items), b->hjobs.data(), b->hjobs.size() * sizeof(BatchJob));
+    std::memcpy(img + (b->o_groups - b->o_items), b->hgroups.data(), b->hgroups.size() * sizeof(BatchGroup));
+    std::memcpy(img + (b->o_zptr - b->o_items), b->hzptrs.data(), b->hzptrs.size() * sizeof(void*));
+    StageHeader hdr{kStageMagic, 0u};
+    std::memcpy(h_stage, &hdr, sizeof hdr);
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(b->d_mem + b->o_items, img, b->o_zero - b->o_items, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = enqueue(b, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((char*)h_stage + offsetof(StageHeader, flag), b->d_zero + kCtrGroups + b->ngroups,
+                           sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    // the plans record the work's completion on `stream` (zm_destroy waits for it)
+    for (int g = 0; e == hipSuccess && st == ZM_OK && g < b->ngroups; ++g)
+        st = note_call(b->plans[b->members[g][0]], s);
+    destroy_batch(b);
+    if (e != hipSuccess) return hip_fail(e, "batch upload / launch");
+    if (st == ZM_OK) log_msg(kLogDebug, "zm_moments_batch_async: %d jobs, stream %p", njobs, stream);
+    return st;
+}
+
+zm_status zm_batch_stage_status(const void* h_stage) {
+    if (!h_stage) return fail(ZM_EINVAL, "null staging buffer");
+    StageHeader hdr;
+    std::memcpy(&hdr, h_stage, sizeof hdr);
+    if (hdr.magic != kStageMagic) return fail(ZM_EINVAL, "not a staging buffer of zm_moments_batch_async");
+    if (hdr.flag) return fail(ZM_EDEVICE, "batch kernel: a projection item waited past its bound");
+    return ZM_OK;
 }
 
 }  // extern "C"

@@ -275,13 +275,22 @@ class FakeDevice:
 
 class GpuDevice:
     """Runs launches on the library: pinned host frames -> device (copy
-    stream), zm_moments on one of several compute streams, moments -> pinned
-    host buffers (copy stream); an event marks completion."""
+    stream), the moments on one of several compute streams, moments ->
+    pinned host buffers (copy stream); an event marks completion.
 
-    def __init__(self, dtype: str = "f32", n_streams: int = 4, plans=None):
+    mode "per_plan": a launch holds requests of one plan and runs zm_moments
+    on their stacked frames.  mode "persistent": a launch holds the admitted
+    requests of any plans (frame sizes and orders mixed) and runs them as one
+    persistent kernel over a (frame, ring tile) work queue
+    (zm_moments_batch_async, no host wait)."""
+
+    def __init__(self, dtype: str = "f32", n_streams: int = 4, plans=None, mode: str = "per_plan"):
         import torch
 
         import paper_2304_14492_amd as zm
+        if mode not in ("per_plan", "persistent"):
+            raise ValueError(f"unknown mode {mode!r}")
+        self.mode = mode
         self.zm = zm
         self.torch = torch
         self.dtype = dtype
@@ -299,13 +308,16 @@ class GpuDevice:
         return self.plans[key]
 
     def plan_key(self, r: Request):
-        return (r.H, r.W, r.nmax)
+        # the persistent form takes any mix of plans in one launch
+        return () if self.mode == "persistent" else (r.H, r.W, r.nmax)
 
     def request_bytes(self, r: Request) -> int:
         p = self.plan(r.H, r.W, r.nmax)
         return 4 * r.H * r.W + p.workspace_size(1) + 8 * p.num_moments
 
     def launch(self, ln: Launch):
+        if self.mode == "persistent":
+            return self._launch_persistent(ln)
         torch = self.torch
         H, W, nmax = ln.key
         p = self.plan(H, W, nmax)
@@ -340,11 +352,43 @@ class GpuDevice:
         ws.record_stream(cs)
         ln.handle = (ev_done, frames, ws, Z, host_out, ev)
 
+    def _launch_persistent(self, ln: Launch):
+        torch = self.torch
+        cs = self.streams[self.rr % len(self.streams)]
+        self.rr += 1
+        plans = [self.plan(r.H, r.W, r.nmax) for r in ln.reqs]
+        frames = [torch.empty(r.H, r.W, dtype=torch.float32, device="cuda") for r in ln.reqs]
+        outs = [torch.empty(p.num_moments, 2, dtype=torch.float32, device="cuda") for p in plans]
+        host_out = [torch.empty(p.num_moments, 2, dtype=torch.float32, pin_memory=True) for p in plans]
+        ev = self._events.pop() if self._events else [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        with torch.cuda.stream(self.copy_in):
+            ev[0].record(self.copy_in)
+            for f, r in zip(frames, ln.reqs):
+                f.copy_(r.frame, non_blocking=True)
+            ev[1].record(self.copy_in)
+        cs.wait_event(ev[1])
+        ev[2].record(cs)
+        bl = self.zm.BatchLaunch(plans, frames, outs, stream=cs)
+        ev[3].record(cs)
+        self.copy_out.wait_event(ev[3])
+        with torch.cuda.stream(self.copy_out):
+            ev[4].record(self.copy_out)
+            for h, z in zip(host_out, outs):
+                h.copy_(z, non_blocking=True)
+            ev[5].record(self.copy_out)
+        for f in frames:
+            f.record_stream(self.copy_in)
+        for z in outs:
+            z.record_stream(self.copy_out)
+        ln.handle = (ev[5], frames, bl, outs, host_out, ev)
+
     def is_done(self, ln: Launch) -> bool:
         return ln.handle[0].query()
 
     def finish(self, ln: Launch):
         host_out, ev = ln.handle[4], ln.handle[5]
+        if self.mode == "persistent":
+            ln.handle[2].check()  # the run's error flag, back in its staging buffer
         h2d = ev[0].elapsed_time(ev[1]) / 1e3
         comp = ev[2].elapsed_time(ev[3]) / 1e3
         d2h = ev[4].elapsed_time(ev[5]) / 1e3

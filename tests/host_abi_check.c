@@ -52,6 +52,9 @@ static void check_null_arguments(void) {
     CHECK(zm_moments_batch(NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_batch_workspace_size(NULL, 0, &bytes) == ZM_EINVAL);
     CHECK(zm_moments_batch_ws(NULL, 0, NULL, 0, NULL) == ZM_EINVAL);
+    CHECK(zm_batch_stage_size(NULL, 0, &bytes) == ZM_EINVAL);
+    CHECK(zm_moments_batch_async(NULL, 0, NULL, 0, NULL, 0, NULL) == ZM_EINVAL);
+    CHECK(zm_batch_stage_status(NULL) == ZM_EINVAL);
     CHECK(zm_reconstruct(NULL, NULL, 1, NULL, 0, 0, NULL, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_recon_workspace_size(NULL, 1, &bytes) == ZM_EINVAL);
     CHECK(zm_recon_error(NULL, NULL, NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);

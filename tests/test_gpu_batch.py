@@ -189,6 +189,73 @@ def test_caller_workspace_batch_bit_exact(zm, dtype):
         assert torch.equal(z, r)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
+def test_async_launches_bit_exact(zm, dtype):
+    # zm_moments_batch_async: three mixed launches in flight on two streams
+    # (the second and third reuse nothing of the first), each checked through
+    # its staging buffer once its stream has passed it
+    specs = [(256, 30, 31), (512, 100, 32), (384, 50, 33), (1024, 50, 34), (256, 30, 35), (768, 100, 36)]
+    frames = _frames(specs)
+    plans = _plans(zm, specs, dtype)
+    ref = [p.moments(f) for p, f in zip(plans, frames)]
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    for s in (s1, s2):
+        s.wait_stream(torch.cuda.current_stream())
+    runs = []
+    for s, sel in ((s1, [0, 1, 2]), (s2, [3, 4, 5]), (s1, [5, 0, 3, 1])):
+        with torch.cuda.stream(s):
+            bl = zm.BatchLaunch([plans[i] for i in sel], [frames[i] for i in sel], stream=s)
+            ev = torch.cuda.Event()
+            ev.record(s)
+        runs.append((bl, ev, sel))
+    for bl, ev, sel in runs:
+        ev.synchronize()
+        bl.check()
+        for z, i in zip(bl.outs, sel):
+            assert torch.equal(z, ref[i]), (dtype, i)
+
+
+def test_async_launch_arguments(zm):
+    specs = [(256, 30, 41), (512, 50, 42)]
+    frames = _frames(specs)
+    plans = _plans(zm, specs)
+    with pytest.raises(ValueError):  # staging buffer not pinned
+        zm.BatchLaunch(plans, frames, stage=torch.empty(1 << 20, dtype=torch.uint8))
+    outs = [torch.empty(p.num_moments, 2, device="cuda") for p in plans]
+    jobs = zm._jobs(plans, frames, outs)
+    n = zm._sz()
+    assert zm._lib.zm_batch_stage_size(jobs, 2, zm.ctypes.byref(n)) == zm.ZM_OK
+    stage = torch.zeros(n.value, dtype=torch.uint8, pin_memory=True)
+    ws = torch.empty(zm.batch_workspace_size(plans, frames, outs), dtype=torch.uint8, device="cuda")
+    # too small a staging buffer is refused before anything is enqueued
+    assert zm._lib.zm_moments_batch_async(jobs, 2, ws.data_ptr(), ws.numel(), stage.data_ptr(), n.value - 1,
+                                          None) == zm.ZM_EINVAL
+    # a buffer that no launch has written is not a staging buffer
+    assert zm._lib.zm_batch_stage_status(stage.data_ptr()) == zm.ZM_EINVAL
+
+
+def test_async_launch_reports_wait_bound(zm, monkeypatch):
+    # the error flag of a run comes back through the staging buffer: with a
+    # bound of 0 polls a projection item that finds a 4K frame's tiles still
+    # running gives up (the kernel finishes normally)
+    monkeypatch.setenv("ZM_BATCH_SPIN_LIMIT", "0")
+    plan = zm.Plan(200, 2160, 3840, dtype="f32", rings=1080, angles=4096)
+    f = torch.rand(2160, 3840, device="cuda")
+    bl = zm.BatchLaunch([plan], [f])
+    torch.cuda.synchronize()
+    with pytest.raises(zm.ZmError) as e:
+        bl.check()
+    assert e.value.status == zm.ZM_EDEVICE
+    monkeypatch.delenv("ZM_BATCH_SPIN_LIMIT")
+    bl = zm.BatchLaunch([plan], [f])
+    torch.cuda.synchronize()
+    bl.check()
+    ref = plan.moments(f)
+    torch.cuda.synchronize()
+    assert torch.equal(bl.outs[0], ref)
+
+
 def test_destroy_reports_busy(zm):
     # a plan with work in flight, or with a batch built on it, is not freed
     plan = zm.Plan(100, 1024, 1024, dtype="f32")

@@ -19,11 +19,14 @@ def zm():
     return m
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16x2"])
-def test_mixed_stream_equals_alone(zm, dtype):
+@pytest.mark.parametrize("dtype,mode", [("f32", "per_plan"), ("bf16x2", "per_plan"), ("f32", "persistent"),
+                                        ("bf16x2", "persistent")])
+def test_mixed_stream_equals_alone(zm, dtype, mode):
+    # per_plan: a launch per plan group; persistent: the admitted requests of
+    # all sizes and orders in one persistent launch (zm_moments_batch_async)
     from paper_2304_14492_amd import serve
     reqs = serve.make_requests(48, qps=4000.0, seed=5, pool_per_size=2)
-    dev = serve.GpuDevice(dtype=dtype, n_streams=4)
+    dev = serve.GpuDevice(dtype=dtype, n_streams=4, mode=mode)
     dev.warm({(r.H, r.W, r.nmax) for r in reqs})
     budget = 1 << 30
     sch = serve.Scheduler(dev, budget, max_inflight=6, max_batch=4)
