@@ -20,16 +20,21 @@ value, unit, ms_per_step, config, ...):
                  useful and issued MFMA fractions and its operand HBM rate
   cpu_baseline   the FP64 CPU oracle on a bounded sample, scaled to images/s,
                  on all host threads and (single_thread) on one
+  batch_sweep    the FP32 step at batch 1, 8 and 128 (kernel times by HIP
+                 events; the spectra kernel's HBM fraction)
   batch_form     64 mixed square frames (sides 256..2048, N_max 30/50/100) in
                  one persistent launch replayed from a HIP graph, with its HBM
-                 rate (algorithmic bytes of the whole batch); beside it the
-                 same frames as per-plan zm_moments launches
+                 rate (algorithmic bytes of the whole batch), tuned and
+                 untuned shape; beside it the same frames as per-plan
+                 zm_moments launches, and 64 4K frames of one plan
   latency        the serving form: Poisson arrivals at a fixed rate of
                  640x480 / 1080p / 4K frames (N_max 30/100/200) from pinned host
                  memory, continuous batching under an HBM budget; p50 / p99 /
-                 p99.9 latency (arrival -> moments in host memory), FP32 and
+                 p99.9 latency (arrival -> moments in host memory) with the
+                 per-request split (queue, copies, compute, other), FP32 and
                  split-BF16 projection; saturation throughput from a burst,
-                 then streams at the fixed rate and at 50 % / 80 % of it
+                 then streams at the fixed rate and at 50 % / 80 % of it; and
+                 (persistent) each admission round as one persistent launch
   reconstruction eq. (9) of one 4K frame at N_max 200 at the pixel centres
                  (FP64 rate vs the FP64 vector peak) and at the polar nodes
   cartesian_single_moment
@@ -478,6 +483,7 @@ def main():
     ap.add_argument("--requests", type=int, default=10000,
                     help="at most this many requests per serving run (0 skips serving)")
     ap.add_argument("--no-batch-form", action="store_true")
+    ap.add_argument("--no-batch-sweep", action="store_true", help="skip the FP32 step at batch 1, 8 and 128")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction timing")
     ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian single-moment timing")
     ap.add_argument("--no-dedup", action="store_true", help="skip the de-duplication timing")
@@ -571,6 +577,20 @@ def main():
             print(f"[bench] {dt}: {ms2:.3f} ms/step, projection {r2['proj_ms']:.3f} ms", file=sys.stderr,
                   flush=True)
             del r2
+    if not args.no_batch_sweep and args.dtype == "f32":
+        # the same FP32 step at other batch sizes (kernel times by HIP events, as above)
+        res["batch_sweep"] = []
+        for b in (1, 8, 128):
+            torch.cuda.empty_cache()
+            rb = run_gpu(b, args.steps, args.warmup, "f32")
+            msb = rb["total_ms"] / args.steps
+            res["batch_sweep"].append({"batch": b, "images_per_s": round(b / (msb / 1e3), 1),
+                                       "ms_per_step": round(msb, 4), "spectra_ms": round(rb["spec_ms"], 4),
+                                       "spectra_hbm_frac": round(spectra_bytes_per_frame() * b /
+                                                                 (rb["spec_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                                       "projection_ms": round(rb["proj_ms"], 4)})
+            del rb
+        print(f"[bench] batch sweep: {res['batch_sweep']}", file=sys.stderr, flush=True)
     if not args.no_batch_form:
         torch.cuda.empty_cache()
         res["batch_form"] = batch_form(args.steps)
