@@ -97,7 +97,8 @@ typedef struct {
     size_t workspace_bytes_fixed;     /* per-call workspace independent of batch        */
 } zm_plan_info_t;
 
-/* Number of stored moments for n_max: (n_max/2+1)(n_max/2+1) for even n_max,
+/* Number of stored moments for n_max (the pairs 0 <= m <= n <= n_max with
+ * n - m even of eq. (2), Sec. 2): (n_max/2+1)(n_max/2+1) for even n_max,
  * (n_max+1)(n_max+3)/4 for odd n_max; -1 if n_max < 0. */
 int zm_num_moments(int n_max);
 
@@ -123,6 +124,8 @@ zm_status zm_plan(int n_max, int H, int W, zm_dtype dtype, int neumann, zm_plan_
  * ring-node and reconstruction entry points serve them. */
 zm_status zm_plan_ex(const zm_plan_desc* desc, zm_plan_t* out);
 
+/* The plan's grid and sizes (its polar grid for eq. (1): R rings, A angles;
+ * resident and workspace bytes).  ZM_EINVAL on null arguments. */
 zm_status zm_plan_info(zm_plan_t plan, zm_plan_info_t* out);
 
 /* Copy the FP64 radial table R_nm(rho_r) produced by eq. (7) (unweighted) to
@@ -139,10 +142,14 @@ zm_status zm_radial_table(zm_plan_t plan, double* host_out, size_t n_elems);
  * without an operand (n_max > 255).  Synchronous. */
 zm_status zm_operand_table(zm_plan_t plan, double* host_out, size_t n_elems);
 
-/* Copy the plan's ring nodes rho_r and weights w_r (FP64, R each) to host. */
+/* Copy the plan's ring nodes rho_r and weights w_r (FP64, R each) to host:
+ * the radial quadrature of eq. (1) on the polar grid (Sec. 2.5), midpoint
+ * or Gauss-Legendre as the plan's rule says.  n_elems >= R.  Synchronous. */
 zm_status zm_ring_nodes(zm_plan_t plan, double* rho_out, double* w_out, size_t n_elems);
 
-/* Bytes of device workspace zm_moments needs for `batch` frames. */
+/* Bytes of device workspace zm_moments needs for `batch` frames: the ring
+ * spectra (the angular sums of eq. (1)) of every frame, plus per-frame
+ * scales for ZM_F16X2.  No device call. */
 zm_status zm_workspace_size(zm_plan_t plan, int batch, size_t* bytes);
 
 /* Moments of `batch` frames by eq. (1) (Sec. 2) on the plan's polar grid:
