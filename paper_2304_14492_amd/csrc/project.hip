@@ -58,14 +58,14 @@ ProjArgs make_proj_args(const zm_plan_s* p, const void* F, const float* fmax, in
 // row blocks of one m (which all read the same spectra slice F[., m, ., .])
 // then share one L2 and the slice comes from HBM once.
 // A workgroup of four waves: with NP = 1 each wave owns one output block and
-// runs through its rings; with NP = kChunks the four waves share one block,
-// one ring chunk each, and add their partial sums in chunk order.  Either way
-// the moments are the same bits (see project_unit), so the launch picks the
-// split by size: one block per wave while the blocks fill the chip's SIMDs,
-// four waves per block below that (small batches).
+// runs through its rings; with NP = 2 two waves share a block (chunks 0-1
+// and 2-3); with NP = kChunks the four waves share one block, one ring chunk
+// each; the partial sums are added in chunk order.  Either way the moments
+// are the same bits (see project_unit), so the launch picks the split by
+// size.
 template <int DT, int NP>
 __global__ __launch_bounds__(64 * kWaves) void project_kernel(ProjArgs a, int n_blocks) {
-    __shared__ __attribute__((aligned(16))) char red[NP == 1 ? 16 : chunk_lds_bytes<DT>()];
+    __shared__ __attribute__((aligned(16))) char red[NP == 1 ? 16 : (kWaves / NP) * chunk_lds_bytes<DT>()];
     const int per_xcd = (int)(gridDim.x / 8);
     const int blk = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
     if (blk >= n_blocks) return;  // whole workgroups only: the waves of a block meet at barriers
@@ -73,19 +73,32 @@ __global__ __launch_bounds__(64 * kWaves) void project_kernel(ProjArgs a, int n_
         const int unit = blk * kWaves + (threadIdx.x >> 6);
         if (unit < a.n_units) project_unit<DT, 1>(a, unit, threadIdx.x & 63, 0, true, red);
     } else {
-        project_unit<DT, NP>(a, blk, threadIdx.x & 63, threadIdx.x >> 6, true, red);
+        // kWaves / NP blocks per workgroup, NP waves each; a wave of a block
+        // past the end computes nothing but still meets the barriers
+        const int w = threadIdx.x >> 6, unit = blk * (kWaves / NP) + w / NP;
+        project_unit<DT, NP>(a, unit < a.n_units ? unit : 0, threadIdx.x & 63, w % NP, unit < a.n_units,
+                             red + (size_t)(w / NP) * chunk_lds_bytes<DT>());
     }
 }
 
 static_assert(kWaves == kChunks, "a workgroup of one block holds one wave per chunk");
 
-// output blocks from which one wave per block fills the MI355X's 1024 SIMDs
+// Waves per output block by launch size (measured at 4K, N_max 200): four
+// below 1,024 blocks (small batches, e.g. 425 blocks at batch 1); one from
+// 1,024 (batch 64: 1,700 blocks, which fill the MI355X's 1,024 SIMDs about
+// twice); two from 2,048 (batch 128: one wave per block left a tail of
+// waves per SIMD, 0.131 against 0.111 ms).
 constexpr int kBlocksOneWave = 1024;
+constexpr int kBlocksTwoWaves = 2048;
 
 template <int DT>
 hipError_t launch_dt(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
     ProjArgs a = make_proj_args(p, F, fmax, batch, Z, nullptr);
-    if (a.n_units >= kBlocksOneWave) {
+    if (a.n_units >= kBlocksTwoWaves) {
+        const int blocks = (a.n_units + 1) / 2;
+        const int blocks8 = (blocks + 7) / 8 * 8;
+        hipLaunchKernelGGL((project_kernel<DT, 2>), dim3(blocks8), dim3(64 * kWaves), 0, s, a, blocks);
+    } else if (a.n_units >= kBlocksOneWave) {
         const int blocks = (a.n_units + kWaves - 1) / kWaves;
         const int blocks8 = (blocks + 7) / 8 * 8;
         hipLaunchKernelGGL((project_kernel<DT, 1>), dim3(blocks8), dim3(64 * kWaves), 0, s, a, blocks);

@@ -20,9 +20,10 @@ constexpr int kWaves = 4;
 
 // The rings of an output block are summed in kChunks contiguous chunks whose
 // partial sums are added in chunk order, ((c0 + c1) + c2) + c3, whichever
-// waves compute them: one wave running through all chunks (NP = 1) or one
-// wave per chunk meeting in LDS (NP = kChunks).  The result is the same bits
-// either way, so a launch can pick the split that suits its size.
+// waves compute them: one wave running through all chunks (NP = 1), two
+// waves (NP = 2: the first keeps c0 + c1, the second c2 and c3 apart) or one
+// wave per chunk (NP = kChunks), meeting in LDS.  The result is the same bits
+// every way, so a launch can pick the split that suits its size.
 constexpr int kChunks = 4;
 
 // First ring of chunk c: the block's K steps (16 rings, or 32 for the 16-bit
@@ -75,7 +76,7 @@ __device__ __forceinline__ T* zbase(const ProjArgs& a, int fr) {
 // chunk_lds_bytes<DT>() of LDS.
 template <int DT, int NP>
 __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int lane, int part, bool valid, void* red) {
-    static_assert(NP == 1 || NP == kChunks, "one wave per block or one per chunk");
+    static_assert(NP == 1 || NP == 2 || NP == kChunks, "1, 2 or kChunks waves per block");
     using Acc = typename std::conditional<DT == ZM_F64, doublex4, floatx4>::type;
     using Val = typename std::conditional<DT == ZM_F64, double, float>::type;
     if (!valid) unit = 0;
@@ -114,25 +115,30 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
 
     // this wave's chunks [c0, c1) and their rings [kb, ke)
     constexpr int STEP = (DT == ZM_F64 || DT == ZM_F32) ? 16 : 32;
-    const int c0 = NP == 1 ? 0 : part, c1 = NP == 1 ? kChunks : part + 1;
+    const int c0 = part * (kChunks / NP), c1 = c0 + kChunks / NP;
     const int kb = chunk_edge(Rp, STEP, c0);
     const int ke = valid ? chunk_edge(Rp, STEP, c1) : kb;
     Acc acc[2][2] = {};
-    Acc tot[2][2] = {};  // NP = 1: sum of the finished chunks, in order
+    Acc tot[2][2] = {};  // sum of the finished leading chunks, in order (NP = 1; wave 0 of NP = 2)
     Val* rd = (Val*)red;
-    // the accumulators hold chunk c: fold them into the total (NP = 1) or
-    // hand them to LDS (NP = kChunks), and clear them for the next chunk
+    // the accumulators hold chunk c: fold them into the running total (NP =
+    // 1, and chunks 0 and 1 of NP = 2, whose total then goes to LDS slot 0)
+    // or hand them to LDS slot c, and clear them for the next chunk
     auto flush = [&](int c) {
+        const bool running = NP == 1 || (NP == 2 && part == 0);
 #pragma unroll
         for (int s = 0; s < 2; ++s)
 #pragma unroll
             for (int u = 0; u < 2; ++u) {
-                if constexpr (NP == 1) {
+                if (running) {
                     if (c == 0)
                         tot[s][u] = acc[s][u];
                     else
 #pragma unroll
                         for (int v = 0; v < 4; ++v) tot[s][u][v] = tot[s][u][v] + acc[s][u][v];
+                    if (NP == 2 && c == 1)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) rd[((s * 2 + u) * 4 + v) * 64 + lane] = tot[s][u][v];
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) rd[(c * 16 + (s * 2 + u) * 4 + v) * 64 + lane] = acc[s][u][v];
@@ -316,17 +322,23 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
                 for (int v = 0; v < 4; ++v) store(s, u, v, tot[s][u][v]);
     } else {
         __syncthreads();
-        const int v = part;  // the wave of chunk p writes vector element p of every accumulator
+        // wave p writes vector elements [p, p + 1) x (kChunks / NP) of every
+        // accumulator: ((c0 + c1) + c2) + c3, with slot 0 holding c0 + c1
+        // already when NP = 2
 #pragma unroll
-        for (int s = 0; s < 2; ++s)
+        for (int vv = 0; vv < kChunks / NP; ++vv) {
+            const int v = part * (kChunks / NP) + vv;
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int e = (s * 2 + u) * 4 + v;
-                Val sum = rd[(0 * 16 + e) * 64 + lane];
+            for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int w = 1; w < kChunks; ++w) sum += rd[(w * 16 + e) * 64 + lane];
-                store(s, u, v, sum);
-            }
+                for (int u = 0; u < 2; ++u) {
+                    const int e = (s * 2 + u) * 4 + v;
+                    Val sum = rd[(0 * 16 + e) * 64 + lane];
+#pragma unroll
+                    for (int w = NP == 2 ? 2 : 1; w < kChunks; ++w) sum += rd[(w * 16 + e) * 64 + lane];
+                    store(s, u, v, sum);
+                }
+        }
         __syncthreads();
     }
 }
