@@ -251,6 +251,25 @@ def test_batch_equals_single_bit_exact(zm):
             assert np.array_equal(Zi, Zb[i]), (dtype, i)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16x2", "f16x2", "f64"])
+def test_projection_splits_bit_identical(zm, dtype):
+    # N_max 100 has 138 projection items: batch 1 runs four waves per output
+    # block (138 blocks), batch 128 one wave per block (8 column blocks: 1,104
+    # blocks), batch 300 two waves per block (19 column blocks: 2,622 blocks);
+    # the ring chunks are summed in the same order every way
+    real = np.float64 if dtype == "f64" else np.float32
+    base = np.stack([synth.make_frame(synth.FrameSpec(96, 96, blobs=5), seed=300 + i) for i in range(6)])
+    plan = zm.Plan(100, 96, 96, dtype=dtype)
+    frames = base[np.arange(300) % 6].astype(real)
+    Z300 = gpu_moments(zm, plan, frames)
+    Z128 = gpu_moments(zm, plan, frames[:128])
+    for i in range(6):
+        Z1 = gpu_moments(zm, plan, frames[i:i + 1])[0]
+        assert np.array_equal(Z1, Z128[i]) and np.array_equal(Z1, Z300[i]), (dtype, i)
+    for i in (127, 299):
+        assert np.array_equal(Z300[i], Z300[i % 6]), (dtype, i)
+
+
 def test_strided_batch_and_zero_batch(zm):
     big = np.zeros((3, 80, 100), dtype=np.float32)
     big[:, :, :90] = np.stack([synth.make_frame(synth.FrameSpec(80, 90, blobs=4), seed=s) for s in (1, 2, 3)])
