@@ -22,6 +22,9 @@ value, unit, ms_per_step, config, ...):
                  on all host threads and (single_thread) on one
   batch_sweep    the FP32 step at batch 1, 8 and 128 (kernel times by HIP
                  events; the spectra kernel's HBM fraction)
+  resample_alone the same FP32 step as two launches: the resampler alone
+                 (zm_resample_polar, polar image written to HBM) and moments
+                 from that image; times and bit-identity with the fused step
   batch_form     64 mixed square frames (sides 256..2048, N_max 30/50/100) in
                  one persistent launch replayed from a HIP graph, with its HBM
                  rate (algorithmic bytes of the whole batch), tuned and
@@ -208,6 +211,44 @@ def run_gpu(batch, steps, warmup, dtype):
     proj_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
     out = dict(total_ms=total_ms, wall_s=wall, spec_ms=spec_ms, proj_ms=proj_ms, Z=Z, plan=plan)
     return out
+
+
+def resample_alone(batch, steps, warmup):
+    """The same step split in two: the resampler alone (zm_resample_polar, tiles
+    of 32 rings x 64 angles, polar image written to HBM) then moments from the
+    polar image (from-polar transform + projection).  Same moments, bit for bit."""
+    import torch
+    import paper_2304_14492_amd as zm
+    plan = zm.Plan(NMAX, H, W, dtype="f32", rings=RINGS, angles=ANGLES)
+    base = make_frames(batch)
+    frames = torch.empty(batch, H, W, dtype=torch.float32, device="cuda")
+    for i in range(batch):
+        frames[i].copy_(torch.from_numpy(base[i % len(base)]))
+    ws = plan.workspace(batch)
+    P = torch.empty(batch, RINGS, ANGLES, dtype=torch.float32, device="cuda")
+    Z1 = torch.empty(batch, plan.num_moments, 2, dtype=torch.float32, device="cuda")
+    Z2 = torch.empty_like(Z1)
+    stream = torch.cuda.current_stream()
+    plan.moments(frames, out=Z1, workspace=ws, stream=stream)
+    for _ in range(warmup):
+        plan.resample_polar(frames, out=P, stream=stream)
+        plan.moments_polar(P, out=Z2, workspace=ws, stream=stream)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(Z1, Z2))
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    for k in range(steps):
+        ev[k][0].record(stream)
+        plan.resample_polar(frames, out=P, stream=stream)
+        ev[k][1].record(stream)
+        plan.moments_polar(P, out=Z2, workspace=ws, stream=stream)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    res_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    pol_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    polar_bytes = batch * RINGS * ANGLES * 4
+    return {"resample_ms": round(res_ms, 4), "moments_from_polar_ms": round(pol_ms, 4),
+            "step_ms": round(res_ms + pol_ms, 4), "polar_image_bytes": polar_bytes,
+            "resample_write_tbs": round(polar_bytes / (res_ms / 1e3) / 1e12, 3), "bit_identical_to_fused": same}
 
 
 def cpu_baseline(budget_s):
@@ -484,6 +525,7 @@ def main():
                     help="at most this many requests per serving run (0 skips serving)")
     ap.add_argument("--no-batch-form", action="store_true")
     ap.add_argument("--no-batch-sweep", action="store_true", help="skip the FP32 step at batch 1, 8 and 128")
+    ap.add_argument("--no-two-pass", action="store_true", help="skip the resampler-alone + from-polar timing")
     ap.add_argument("--no-recon", action="store_true", help="skip the reconstruction timing")
     ap.add_argument("--no-cartesian", action="store_true", help="skip the Cartesian single-moment timing")
     ap.add_argument("--no-dedup", action="store_true", help="skip the de-duplication timing")
@@ -591,6 +633,10 @@ def main():
                                        "projection_ms": round(rb["proj_ms"], 4)})
             del rb
         print(f"[bench] batch sweep: {res['batch_sweep']}", file=sys.stderr, flush=True)
+    if not args.no_two_pass and args.dtype == "f32":
+        torch.cuda.empty_cache()
+        res["resample_alone"] = resample_alone(args.batch, args.steps, args.warmup)
+        print(f"[bench] resampler alone: {res['resample_alone']}", file=sys.stderr, flush=True)
     if not args.no_batch_form:
         torch.cuda.empty_cache()
         res["batch_form"] = batch_form(args.steps)

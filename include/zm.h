@@ -221,6 +221,23 @@ zm_status zm_count_nonfinite(zm_plan_t plan, const void* d_Z, int batch, int* d_
 zm_status zm_moments_polar(zm_plan_t plan, const void* d_polar, int batch, void* d_Z, void* d_ws,
                            size_t ws_bytes, zm_stream_t stream);
 
+/* The resampler alone (Sec. 2.5): bilinear samples of each frame on the
+ * plan's polar grid, P[b][r][a] = f^(rho_r, 2 pi a / A) for r < R, a < A,
+ * the inputs of the angular sum of eq. (1).  The values are the ones the
+ * moment entry points sample, bit for bit, so zm_moments_polar on d_polar
+ * gives the same moments as zm_moments on the frames.
+ *   d_images     : device, as for zm_moments (H x W row-major frames,
+ *                  frame b at d_images + b * image_stride elements; float,
+ *                  or double for ZM_F64).
+ *   d_polar      : device, caller-owned, [batch][R][A] of the same type,
+ *                  overwritten.
+ * Requires A a power of two with 256 <= A <= 4096 (ZM_EUNSUPPORTED
+ * otherwise).  Asynchronous on `stream`; allocates nothing.  Errors:
+ * ZM_EINVAL (null plan or pointers, batch < 0 or > 65535, image_stride <
+ * H * W with batch > 1), ZM_EDEVICE (launch failure). */
+zm_status zm_resample_polar(zm_plan_t plan, const void* d_images, int batch, long long image_stride, void* d_polar,
+                            zm_stream_t stream);
+
 /* ---- Batched persistent form: frames of different sizes and orders ---- */
 
 /* One frame of a mixed batch: its plan (FP32-family dtype, n_max <= 255,

@@ -78,6 +78,7 @@ _SIGS = {
     "zm_workspace_size": (ctypes.c_int, [_vp, ctypes.c_int, ctypes.POINTER(_sz)]),
     "zm_moments": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp, _sz, _vp]),
     "zm_moments_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, _sz, _vp]),
+    "zm_resample_polar": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp]),
     "zm_moments_static": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_longlong, _vp, _vp]),
     "zm_static_scratch_bytes": (_sz, []),
     "zm_count_nonfinite": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
@@ -399,6 +400,23 @@ class Plan:
         _check(_lib.zm_project(self._h, batch, _vp(out.data_ptr()), _vp(workspace.data_ptr()),
                                workspace.numel(), _stream_handle(stream)), "zm_project")
         return out
+
+    def resample_polar(self, frames, out=None, stream=None):
+        """The resampler alone: frames [B, H, W] -> polar image [B, rings, angles] (Sec. 2.5)."""
+        import torch
+        squeeze = frames.dim() == 2
+        if squeeze:
+            frames = frames.unsqueeze(0)
+        self._check_frames(frames)
+        B = frames.shape[0]
+        if out is None:
+            out = torch.empty(B, self.rings, self.angles, dtype=self._real_dtype(), device=frames.device)
+            _keep_alive(stream, out)
+        _need(out, "out", shape=(B, self.rings, self.angles), dtype=self._real_dtype(), device=self.device)
+        _check(_lib.zm_resample_polar(self._h, _vp(frames.data_ptr()), B,
+                                      frames.stride(0) if B > 1 else self.H * self.W, _vp(out.data_ptr()),
+                                      _stream_handle(stream)), "zm_resample_polar")
+        return out[0] if squeeze else out
 
     def moments_polar(self, polar, out=None, workspace=None, stream=None):
         """polar: CUDA tensor [B, rings, angles], contiguous."""

@@ -14,7 +14,7 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libzm.so")
 
 SOURCES = ["plan.cpp", "zrp_table.hip", "polar_fft.hip", "project.hip", "reconstruct.hip", "batch.hip",
-           "cartesian.hip", "diag.cpp"]
+           "cartesian.hip", "resample.hip", "diag.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

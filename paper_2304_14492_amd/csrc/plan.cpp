@@ -666,6 +666,20 @@ zm_status zm_moments_polar(zm_plan_t p, const void* d_polar, int batch, void* d_
     return noted(st, p, batch, stream, "zm_moments_polar");
 }
 
+zm_status zm_resample_polar(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_polar,
+                            zm_stream_t stream) {
+    if (!p) return fail(ZM_EINVAL, "null plan");
+    if (batch < 0 || batch > 65535) return fail(ZM_EINVAL, "batch must be in [0, 65535]");
+    if (batch == 0) return ZM_OK;
+    if (!d_images || !d_polar) return fail(ZM_EINVAL, "null input or output pointer");
+    if (batch > 1 && image_stride < (long long)p->H * p->W) return fail(ZM_EINVAL, "image_stride must be >= H * W");
+    if (!resample_supported(p->A)) return fail(ZM_EUNSUPPORTED, "the resampler needs angles a power of two in [256, 4096]");
+    ZM_DEVICE(p->device);
+    hipError_t e = launch_resample(p, d_images, image_stride, batch, d_polar, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "resample kernel launch");
+    return noted(ZM_OK, p, batch, stream, "zm_resample_polar");
+}
+
 size_t zm_static_scratch_bytes(void) { return kStaticScratchBytes; }
 
 zm_status zm_moments_static(zm_plan_t p, const void* d_images, int batch, long long image_stride, void* d_Z,

@@ -155,6 +155,8 @@ hipError_t launch_polar_fft(const zm_plan_s* p, const void* img, long long strid
 hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z,
                           hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s);
+bool resample_supported(int A);
+hipError_t launch_resample(const zm_plan_s* p, const void* img, long long stride, int batch, void* P, hipStream_t s);
 hipError_t launch_count_nonfinite(const zm_plan_s* p, const void* Z, int batch, int* counts, hipStream_t s);
 hipError_t launch_recon_polar(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s);
 hipError_t launch_recon_cart(const zm_plan_s* p, const void* Z, int batch, void* out, int one_sided, hipStream_t s);

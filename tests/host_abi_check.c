@@ -43,6 +43,7 @@ static void check_null_arguments(void) {
     CHECK(zm_spectra(NULL, NULL, 1, 0, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_project(NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);
     CHECK(zm_moments_polar(NULL, NULL, 1, NULL, NULL, 0, NULL) == ZM_EINVAL);
+    CHECK(zm_resample_polar(NULL, NULL, 1, 0, NULL, NULL) == ZM_EINVAL);
     CHECK(zm_batch_create(NULL, 0, 0, NULL) == ZM_EINVAL);
     CHECK(zm_batch_run(NULL, NULL) == ZM_EINVAL);
     CHECK(zm_batch_update(NULL, NULL, 0) == ZM_EINVAL);

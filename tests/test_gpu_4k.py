@@ -7,7 +7,9 @@ distinct seeded frames are tiled over the batch; all 10201 moments of the
 four are checked against the FP64 oracle (gates: FP32 projection 1e-5,
 split BF16 and FP16 1e-4 relative L2, and per n-band within
 errmodel.GATE_SIGMAS standard deviations of the modelled rounding error),
-and every copy of a frame in the batch must be bit-identical to the first.
+and every copy of a frame in the batch must be bit-identical to the first,
+as must the moments from the resampler alone followed by the from-polar
+transform.
 Pixels beyond D/2 + 1.5 px of the centre are NaN, so any read outside the
 disk footprint would show.
 """
@@ -72,6 +74,13 @@ def test_4k_batch64_all_moments(zm, frames_and_reference, dtype, tol):
         assert max(r[4] for r in rows) <= errmodel.GATE_SIGMAS, (dtype, i, rows)
     for i in range(DISTINCT, BATCH):
         assert np.array_equal(Z[i], Z[i % DISTINCT]), (dtype, i)
+    # the resampler alone (tiles of 32 rings) then the from-polar transform
+    # give the same bits as the fused resample + FFT
+    P = plan.resample_polar(dev)
+    Zp = plan.moments_polar(P)
+    torch.cuda.synchronize()
+    assert torch.equal(Zp, Zt), dtype
+    del P, Zp
     # a frame alone gives the same bits (the batch of 64 runs the projection
     # one wave per output block, a single frame four waves per block)
     for i in range(2):

@@ -27,7 +27,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2304_14492_amd", "csrc")
 SOURCES = ["plan.cpp", "zrp_table.hip", "polar_fft.hip", "project.hip", "reconstruct.hip", "batch.hip",
-           "cartesian.hip", "diag.cpp"]
+           "cartesian.hip", "resample.hip", "diag.cpp"]
 HIPCC = "/opt/rocm/bin/hipcc"
 CLANG = "/opt/rocm/llvm/bin/clang"
 CLANGXX = "/opt/rocm/llvm/bin/clang++"
