@@ -257,7 +257,12 @@ enum {
                               the batch on the given frames); the choice is cached per batch signature
                               in-process and, if the environment variable ZM_TUNE_CACHE names a file, in
                               that file */
-    ZM_BATCH_NO_GRAPH = 2  /* launch directly instead of replaying a captured HIP graph */
+    ZM_BATCH_NO_GRAPH = 2, /* launch directly instead of replaying a captured HIP graph */
+    ZM_BATCH_PER_PLAN = 4  /* run each plan's frames as the standalone launches (resample + FFT, then
+                              projection: the kernels of zm_moments) instead of the persistent kernel;
+                              needs every plan's frames at one stride (e.g. slices of one array) and
+                              falls back to the persistent kernel otherwise.  ZM_BATCH_AUTOTUNE also
+                              times this route when the frames allow it */
 };
 
 /* Build the work queue of eq. (1) for all jobs (stage 1: fused resample +
@@ -266,12 +271,15 @@ enum {
  * capture [counter reset + persistent kernel] in a HIP graph.  Synchronous.
  * Each frame's moments are bit-identical to zm_moments on that frame alone,
  * whatever the shape.  Without ZM_BATCH_AUTOTUNE the shape is grid 2 x CUs,
- * costliest tiles first. */
+ * costliest tiles first (or the per-plan launches with ZM_BATCH_PER_PLAN). */
 zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out);
 /* Run the batch on `stream` (asynchronous; one graph launch). */
 zm_status zm_batch_run(zm_batch_t batch, zm_stream_t stream);
 /* Point the batch at new frames / outputs (same plans, same order); waits for
- * the batch's last run to complete first (nothing else on the device). */
+ * the batch's last run to complete first (nothing else on the device).  A
+ * batch on the per-plan route captures its launches again (their frame
+ * pointers are launch arguments) and returns to the persistent kernel if the
+ * new frames are not at one stride per plan. */
 zm_status zm_batch_update(zm_batch_t batch, const zm_job* jobs, int njobs);
 /* Wait for the batch's last run and report ZM_EDEVICE if a stage-2 item of
  * it waited past its bound (a failed dependency; never expected).  The bound
@@ -279,9 +287,10 @@ zm_status zm_batch_update(zm_batch_t batch, const zm_job* jobs, int njobs);
  * ZM_BATCH_SPIN_LIMIT, read by zm_batch_create, replaces it (a small value
  * exercises this error path in tests; the kernel still finishes normally). */
 zm_status zm_batch_check(zm_batch_t batch);
-/* Chosen shape: persistent grid size, item order (0 = costliest tiles first,
- * 1 = natural), and the queue length and device bytes owned by the batch
- * (any pointer may be NULL). */
+/* Chosen shape: persistent grid size (0 when the batch runs as per-plan
+ * launches), item order (0 = costliest tiles first, 1 = natural), and the
+ * queue length and device bytes owned by the batch (any pointer may be
+ * NULL). */
 zm_status zm_batch_config(zm_batch_t batch, int* grid, int* order, int* n_items, size_t* device_bytes);
 /* Waits for the batch's last run, then frees the batch. */
 zm_status zm_batch_destroy(zm_batch_t batch);

@@ -502,7 +502,7 @@ def recon_error(plan, ref, recon, stream=None):
             for r in out]
 
 
-BATCH_AUTOTUNE, BATCH_NO_GRAPH = 1, 2
+BATCH_AUTOTUNE, BATCH_NO_GRAPH, BATCH_PER_PLAN = 1, 2, 4
 
 
 def _jobs(plans, frames, outs):
@@ -529,13 +529,14 @@ class Batch:
     launch, replayed from a captured HIP graph.  frames[i] is a [H, W] float32
     CUDA tensor matching plans[i]; outs[i] is [num_moments, 2] float32."""
 
-    def __init__(self, plans, frames, outs=None, autotune=False, graph=True):
+    def __init__(self, plans, frames, outs=None, autotune=False, graph=True, per_plan=False):
         import torch
         if outs is None:
             outs = [torch.empty(p.num_moments, 2, dtype=p._real_dtype(), device=f.device) for p, f in zip(plans, frames)]
         self.plans, self.frames, self.outs = list(plans), list(frames), list(outs)
         jobs = _jobs(self.plans, self.frames, self.outs)
-        flags = (BATCH_AUTOTUNE if autotune else 0) | (0 if graph else BATCH_NO_GRAPH)
+        flags = (BATCH_AUTOTUNE if autotune else 0) | (0 if graph else BATCH_NO_GRAPH) | \
+            (BATCH_PER_PLAN if per_plan else 0)
         h = _vp()
         _check(_lib.zm_batch_create(jobs, len(jobs), flags, ctypes.byref(h)), "zm_batch_create")
         self._h = h
@@ -558,7 +559,8 @@ class Batch:
         g, o, n, b = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), _sz()
         _check(_lib.zm_batch_config(self._h, ctypes.byref(g), ctypes.byref(o), ctypes.byref(n), ctypes.byref(b)),
                "zm_batch_config")
-        return dict(grid=g.value, order=o.value, n_items=n.value, device_bytes=b.value)
+        return dict(grid=g.value, order=o.value, n_items=n.value, device_bytes=b.value,
+                    route="per_plan" if g.value == 0 else "persistent")
 
     def close(self):
         if getattr(self, "_h", None):

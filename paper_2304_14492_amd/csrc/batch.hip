@@ -404,6 +404,10 @@ struct zm_batch_s {
     QueueInfo qinfo{};
     int grid = 0;
     int order = 0;  // 0: cost-descending stage 1, 1: natural
+    // 0: the persistent kernel; 1: per plan, the standalone resample + FFT and
+    // projection launches (needs each plan's frames at one stride)
+    int route = 0;
+    bool want_per_plan = false;  // ZM_BATCH_PER_PLAN, or the tuner's choice
     // device memory: one block, laid out by batch_layout
     size_t o_items = 0, o_jobs = 0, o_groups = 0, o_zptr = 0, o_zero = 0;
     std::vector<size_t> foff;  // spectra of each group
@@ -483,7 +487,49 @@ zm_status upload_sync(zm_batch_s* b) {
     return ZM_OK;
 }
 
+// Elements between consecutive frames of group g when its frames (in slot
+// order) sit at one stride of at least H * W floats, else -1.
+long long group_stride(const zm_batch_s* b, int g) {
+    const std::vector<int>& m = b->members[g];
+    const zm_plan_s* p = b->plans[m[0]];
+    const long long hw = (long long)p->H * p->W;
+    if (m.size() == 1) return hw;
+    const char* base = (const char*)b->hjobs[m[0]].fa.src;
+    const long long d = (long long)((const char*)b->hjobs[m[1]].fa.src - base);
+    if (d <= 0 || d % (long long)sizeof(float) != 0 || d / (long long)sizeof(float) < hw) return -1;
+    for (size_t k = 2; k < m.size(); ++k)
+        if ((long long)((const char*)b->hjobs[m[k]].fa.src - base) != (long long)k * d) return -1;
+    return d / (long long)sizeof(float);
+}
+
+bool per_plan_ok(const zm_batch_s* b) {
+    for (int g = 0; g < b->ngroups; ++g)
+        if (group_stride(b, g) < 0) return false;
+    return true;
+}
+
+// The per-plan route: counters and FP16 max slots cleared, then for each plan
+// the standalone resample + FFT and projection launches over its frames (the
+// same kernels as zm_moments, so the same bits), spectra in the batch's memory,
+// moments through the batch's output pointers.
+hipError_t enqueue_per_plan(zm_batch_s* b, hipStream_t s) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((b->n_zero + 255) / 256), dim3(256), 0, s, b->d_zero, b->n_zero);
+    hipError_t e = hipGetLastError();
+    for (int g = 0; g < b->ngroups && e == hipSuccess; ++g) {
+        const std::vector<int>& m = b->members[g];
+        const zm_plan_s* p = b->plans[m[0]];
+        const BatchGroup& G = b->hgroups[g];
+        const int n = (int)m.size();
+        float* fmax = const_cast<float*>(G.pa.fmaxbuf);
+        void* F = b->d_mem + b->foff[g];
+        e = zm::launch_polar_fft(p, b->hjobs[m[0]].fa.src, group_stride(b, g), n, F, fmax, 0, s);
+        if (e == hipSuccess) e = zm::launch_project_ptrs(p, F, fmax, n, b->d_zptrs + b->zoff[g], s);
+    }
+    return e;
+}
+
 hipError_t enqueue(zm_batch_s* b, hipStream_t s) {
+    if (b->route == 1) return enqueue_per_plan(b, s);
     hipLaunchKernelGGL(batch_reset_kernel, dim3((b->n_zero + 255) / 256), dim3(256), 0, s, b->d_zero, b->n_zero);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -528,9 +574,10 @@ std::string signature(const zm_batch_s* b) {
     return sig;
 }
 
-// A tuned shape: persistent grid, stage-1 item order.
+// A tuned shape: persistent grid, stage-1 item order, and the route (0:
+// persistent kernel, 1: per-plan launches).
 struct TunedShape {
-    int grid, order;
+    int grid, order, route;
 };
 std::mutex g_tune_mu;
 std::map<std::string, TunedShape> g_tune;  // batch signature -> shape
@@ -545,12 +592,18 @@ void tune_cache_load() {
     if (!f) return;
     char line[8192];
     while (std::fgets(line, sizeof line, f)) {
-        // one entry per line: <grid> <order> <signature>
-        int grid = 0, order = 0, n = 0;
-        if (std::sscanf(line, "%d %d %n", &grid, &order, &n) == 2 && grid > 0 && (order == 0 || order == 1)) {
+        // one entry per line: <grid> <order> <route> <signature> (an entry
+        // without the route field is a persistent-kernel shape)
+        int grid = 0, order = 0, route = 0, n = 0;
+        const int got = std::sscanf(line, "%d %d %d %n", &grid, &order, &route, &n);
+        if (got != 3) {
+            route = 0;
+            if (std::sscanf(line, "%d %d %n", &grid, &order, &n) != 2) continue;
+        }
+        if (grid > 0 && (order == 0 || order == 1) && (route == 0 || route == 1)) {
             std::string sig(line + n);
             while (!sig.empty() && (sig.back() == '\n' || sig.back() == '\r')) sig.pop_back();
-            g_tune[sig] = TunedShape{grid, order};
+            g_tune[sig] = TunedShape{grid, order, route};
         }
     }
     std::fclose(f);
@@ -562,7 +615,7 @@ void tune_cache_store(const std::string& sig, const TunedShape& t) {
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%d %d %s\n", t.grid, t.order, sig.c_str());
+    std::fprintf(f, "%d %d %d %s\n", t.grid, t.order, t.route, sig.c_str());
     std::fclose(f);
 }
 
@@ -577,8 +630,9 @@ zm_status check_error_flag(zm_batch_s* b, hipStream_t s) {
 }
 
 // Times every shape on the batch's own frames (three runs each, the best of
-// the last two) and keeps the fastest; the choice is cached per batch
-// signature.  The moments do not depend on the shape.
+// the last two) and keeps the fastest: persistent grid x item order, and the
+// per-plan launches when every plan's frames sit at one stride.  The choice is
+// cached per batch signature.  The moments do not depend on the shape.
 zm_status autotune(zm_batch_s* b, int cus) {
     const std::string sig = signature(b);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -587,43 +641,66 @@ zm_status autotune(zm_batch_s* b, int cus) {
     if (it != g_tune.end()) {
         b->grid = it->second.grid;
         b->order = it->second.order;
+        b->want_per_plan = b->want_per_plan || it->second.route == 1;
+        b->route = b->want_per_plan && per_plan_ok(b) ? 1 : 0;
         return upload_sync(b);
     }
     hipEvent_t e0, e1;
     ZM_HIP(hipEventCreate(&e0));
     ZM_HIP(hipEventCreate(&e1));
+    auto time_it = [&](float* out) -> zm_status {
+        float ms_best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            ZM_HIP(hipEventRecord(e0, b->stream));
+            hipError_t e = enqueue(b, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "batch launch");
+            ZM_HIP(hipEventRecord(e1, b->stream));
+            ZM_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            ZM_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (rep > 0) ms_best = std::min(ms_best, ms);
+        }
+        *out = ms_best;
+        return ZM_OK;
+    };
     float best = 1e30f;
-    TunedShape bt{2 * cus, 0};
+    TunedShape bt{2 * cus, 0, 0};
     const int grids[3] = {cus, 2 * cus, 4 * cus};
+    b->route = 0;
     for (int order = 0; order < 2; ++order) {
         b->order = order;
         zm_status st = upload_sync(b);
         if (st != ZM_OK) return st;
         for (int gi = 0; gi < 3; ++gi) {
             b->grid = grids[gi];
-            float ms_best = 1e30f;
-            for (int rep = 0; rep < 3; ++rep) {
-                ZM_HIP(hipEventRecord(e0, b->stream));
-                hipError_t e = enqueue(b, b->stream);
-                if (e != hipSuccess) return hip_fail(e, "batch kernel launch");
-                ZM_HIP(hipEventRecord(e1, b->stream));
-                ZM_HIP(hipEventSynchronize(e1));
-                float ms = 0.f;
-                ZM_HIP(hipEventElapsedTime(&ms, e0, e1));
-                if (rep > 0) ms_best = std::min(ms_best, ms);
+            float ms = 0.f;
+            st = time_it(&ms);
+            if (st != ZM_OK) return st;
+            if (ms < best) {
+                best = ms;
+                bt = TunedShape{grids[gi], order, 0};
             }
-            if (ms_best < best) {
-                best = ms_best;
-                bt = TunedShape{grids[gi], order};
-            }
+        }
+    }
+    if (per_plan_ok(b)) {
+        b->route = 1;
+        float ms = 0.f;
+        zm_status st = time_it(&ms);
+        if (st != ZM_OK) return st;
+        if (ms < best) {
+            best = ms;
+            bt.route = 1;
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    b->route = 0;
     zm_status st = check_error_flag(b, b->stream);
     if (st != ZM_OK) return st;
     b->grid = bt.grid;
     b->order = bt.order;
+    b->want_per_plan = b->want_per_plan || bt.route == 1;
+    b->route = b->want_per_plan && per_plan_ok(b) ? 1 : 0;
     tune_cache_store(sig, bt);
     return upload_sync(b);
 }
@@ -820,7 +897,8 @@ extern "C" {
 zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* out) {
     if (!jobs || !out || njobs <= 0) return fail(ZM_EINVAL, "need a non-empty job list and an output pointer");
     *out = nullptr;
-    if (flags & ~(ZM_BATCH_AUTOTUNE | ZM_BATCH_NO_GRAPH)) return fail(ZM_EINVAL, "unknown batch flags");
+    if (flags & ~(ZM_BATCH_AUTOTUNE | ZM_BATCH_NO_GRAPH | ZM_BATCH_PER_PLAN))
+        return fail(ZM_EINVAL, "unknown batch flags");
     zm_batch_s* b = new zm_batch_s();
     zm_status st = batch_layout(b, jobs, njobs);
     if (st != ZM_OK) {
@@ -841,6 +919,8 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
     const int cus = device_cus(b->device);
     b->grid = 2 * cus;
     b->order = 0;
+    b->want_per_plan = (flags & ZM_BATCH_PER_PLAN) != 0;
+    b->route = b->want_per_plan && per_plan_ok(b) ? 1 : 0;
     e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->done, hipEventDisableTiming);
     if (e != hipSuccess) {
@@ -854,9 +934,9 @@ zm_status zm_batch_create(const zm_job* jobs, int njobs, int flags, zm_batch_t* 
         destroy_batch(b);
         return st;
     }
-    log_msg(kLogInfo, "batch %p: %d jobs, %d queue items, %zu device bytes; grid %d, item order %d%s%s", (void*)b,
-            njobs, b->n_items, b->d_bytes, b->grid, b->order, (flags & ZM_BATCH_AUTOTUNE) ? " (tuned)" : "",
-            (flags & ZM_BATCH_NO_GRAPH) ? "" : ", graph captured");
+    log_msg(kLogInfo, "batch %p: %d jobs, %d queue items, %zu device bytes; %s, grid %d, item order %d%s%s",
+            (void*)b, njobs, b->n_items, b->d_bytes, b->route ? "per-plan launches" : "persistent kernel", b->grid,
+            b->order, (flags & ZM_BATCH_AUTOTUNE) ? " (tuned)" : "", (flags & ZM_BATCH_NO_GRAPH) ? "" : ", graph captured");
     *out = b;
     return ZM_OK;
 }
@@ -872,7 +952,14 @@ zm_status zm_batch_update(zm_batch_t b, const zm_job* jobs, int njobs) {
     ZM_HIP(hipEventSynchronize(b->done));  // the descriptors may be in use by the last run
     zm_status st = fill_pointers(b, jobs);
     if (st != ZM_OK) return st;
-    return upload_sync(b);
+    st = upload_sync(b);
+    if (st != ZM_OK) return st;
+    // the per-plan launches take the frame pointers as arguments: capture them
+    // again (frames no longer at one stride fall back to the persistent kernel)
+    const int route = b->want_per_plan && per_plan_ok(b) ? 1 : 0;
+    const bool recapture = b->exec && (route == 1 || b->route == 1);
+    b->route = route;
+    return recapture ? capture(b) : ZM_OK;
 }
 
 zm_status zm_batch_run(zm_batch_t b, zm_stream_t stream) {
@@ -899,7 +986,7 @@ zm_status zm_batch_check(zm_batch_t b) {
 
 zm_status zm_batch_config(zm_batch_t b, int* grid, int* order, int* n_items, size_t* device_bytes) {
     if (!b) return fail(ZM_EINVAL, "null batch");
-    if (grid) *grid = b->grid;
+    if (grid) *grid = b->route == 1 ? 0 : b->grid;
     if (order) *order = b->order;
     if (n_items) *n_items = b->n_items;
     if (device_bytes) *device_bytes = b->d_bytes;

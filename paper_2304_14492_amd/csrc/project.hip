@@ -92,8 +92,9 @@ constexpr int kBlocksOneWave = 1024;
 constexpr int kBlocksTwoWaves = 2048;
 
 template <int DT>
-hipError_t launch_dt(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
-    ProjArgs a = make_proj_args(p, F, fmax, batch, Z, nullptr);
+hipError_t launch_dt(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, void* const* Zptrs,
+                     hipStream_t s) {
+    ProjArgs a = make_proj_args(p, F, fmax, batch, Z, Zptrs);
     if (a.n_units >= kBlocksTwoWaves) {
         const int blocks = (a.n_units + 1) / 2;
         const int blocks8 = (blocks + 7) / 8 * 8;
@@ -152,14 +153,24 @@ hipError_t launch_count_nonfinite(const zm_plan_s* p, const void* Z, int batch, 
     return hipGetLastError();
 }
 
-hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
+static hipError_t launch_any(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z,
+                             void* const* Zptrs, hipStream_t s) {
     switch (p->dtype) {
-        case ZM_F64: return launch_dt<ZM_F64>(p, F, fmax, batch, Z, s);
-        case ZM_F32: return launch_dt<ZM_F32>(p, F, fmax, batch, Z, s);
-        case ZM_BF16X2: return launch_dt<ZM_BF16X2>(p, F, fmax, batch, Z, s);
-        case ZM_F16X2: return launch_dt<ZM_F16X2>(p, F, fmax, batch, Z, s);
+        case ZM_F64: return launch_dt<ZM_F64>(p, F, fmax, batch, Z, Zptrs, s);
+        case ZM_F32: return launch_dt<ZM_F32>(p, F, fmax, batch, Z, Zptrs, s);
+        case ZM_BF16X2: return launch_dt<ZM_BF16X2>(p, F, fmax, batch, Z, Zptrs, s);
+        case ZM_F16X2: return launch_dt<ZM_F16X2>(p, F, fmax, batch, Z, Zptrs, s);
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z, hipStream_t s) {
+    return launch_any(p, F, fmax, batch, Z, nullptr, s);
+}
+
+hipError_t launch_project_ptrs(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* const* Zptrs,
+                               hipStream_t s) {
+    return launch_any(p, F, fmax, batch, nullptr, Zptrs, s);
 }
 
 }  // namespace zm

@@ -154,6 +154,10 @@ hipError_t launch_polar_fft(const zm_plan_s* p, const void* img, long long strid
                             float* fmax, int from_polar, hipStream_t s);
 hipError_t launch_project(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* Z,
                           hipStream_t s);
+// As launch_project with frame b's moments written to Zptrs[b] (a device
+// array of batch output pointers).
+hipError_t launch_project_ptrs(const zm_plan_s* p, const void* F, const float* fmax, int batch, void* const* Zptrs,
+                               hipStream_t s);
 hipError_t launch_zero_u32(unsigned* p, size_t n, hipStream_t s);
 bool resample_supported(int A);
 hipError_t launch_resample(const zm_plan_s* p, const void* img, long long stride, int batch, void* P, hipStream_t s);

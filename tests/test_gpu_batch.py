@@ -62,7 +62,7 @@ def test_config4_batch_graph_autotune(zm):
     plans = _plans(zm, specs)
     b = zm.Batch(plans, frames, autotune=True, graph=True)
     cfg = b.config()
-    assert cfg["grid"] > 0 and cfg["n_items"] > 0
+    assert cfg["n_items"] > 0 and (cfg["grid"] > 0) == (cfg["route"] == "persistent")
     b.run()
     b.check()
     ref = [p.moments(f) for p, f in zip(plans, frames)]
@@ -96,6 +96,79 @@ def test_config4_batch_graph_autotune(zm):
         r = plans[k].moments(new[k])
         torch.cuda.synchronize()
         assert torch.equal(b.outs[k], r)
+    b.close()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_per_plan_route_bit_exact(zm, graph):
+    """ZM_BATCH_PER_PLAN: each plan's frames (slices of one tensor per plan, jobs
+    interleaved across plans) run as the standalone launches; the moments equal
+    zm_moments bit for bit, after an update to other strided frames too, and a
+    batch whose new frames are not at one stride returns to the persistent
+    kernel with the same results."""
+    kinds = [(256, 30, "f32"), (384, 50, "f16x2"), (320, 40, "bf16x2")]
+    counts = [3, 2, 1]
+    plans, stacks = [], []
+    for (side, nmax, dt), n in zip(kinds, counts):
+        plans.append(zm.Plan(nmax, side, side, dtype=dt))
+        st = torch.stack([torch.from_numpy(synth.make_frame(synth.FrameSpec(side, side, blobs=6, noise=True),
+                                                            seed=31 * side + k)) for k in range(n)]).cuda()
+        stacks.append(st)
+    order = [(0, 0), (1, 0), (0, 1), (2, 0), (1, 1), (0, 2)]
+    jplans = [plans[g] for g, _ in order]
+    jframes = [stacks[g][k] for g, k in order]
+    b = zm.Batch(jplans, jframes, graph=graph, per_plan=True)
+    assert b.config()["route"] == "per_plan"
+    b.run()
+    b.check()
+    torch.cuda.synchronize()
+    for p, f, z in zip(jplans, jframes, b.outs):
+        assert torch.equal(z, p.moments(f))
+    # other strided frames: still per-plan launches
+    flipped = [torch.flip(st, dims=[1]).contiguous() for st in stacks]
+    b.update([flipped[g][k] for g, k in order])
+    assert b.config()["route"] == "per_plan"
+    for z in b.outs:
+        z.fill_(float("nan"))
+    b.run()
+    torch.cuda.synchronize()
+    for (g, k), z in zip(order, b.outs):
+        assert torch.equal(z, plans[g].moments(flipped[g][k]))
+    # frames no longer at one stride (the first plan's at frame offsets 0, 1
+    # and 3 of one buffer): the persistent kernel, same bits
+    side0 = kinds[0][0]
+    buf = torch.empty(4, side0, side0, device="cuda")
+    slots = [0, 1, 3]
+    for k in range(3):
+        buf[slots[k]].copy_(stacks[0][k])
+    loose = [buf[slots[k]] if g == 0 else stacks[g][k] for g, k in order]
+    b.update(loose)
+    assert b.config()["route"] == "persistent"
+    for z in b.outs:
+        z.fill_(float("nan"))
+    b.run()
+    b.check()
+    torch.cuda.synchronize()
+    for p, f, z in zip(jplans, loose, b.outs):
+        assert torch.equal(z, p.moments(f))
+    b.close()
+
+
+def test_tuner_times_per_plan_route(zm):
+    """On a homogeneous batch of strided frames the tuner also times the
+    per-plan launches; whichever it keeps, the moments equal zm_moments."""
+    plan = zm.Plan(60, 512, 512, dtype="f32")
+    st = torch.stack([torch.from_numpy(synth.make_frame(synth.FrameSpec(512, 512, blobs=6), seed=k))
+                      for k in range(8)]).cuda()
+    b = zm.Batch([plan] * 8, [st[k] for k in range(8)], autotune=True)
+    cfg = b.config()
+    assert cfg["route"] in ("persistent", "per_plan")
+    b.run()
+    b.check()
+    ref = plan.moments(st)
+    torch.cuda.synchronize()
+    for k in range(8):
+        assert torch.equal(b.outs[k], ref[k])
     b.close()
 
 
