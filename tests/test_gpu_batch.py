@@ -172,6 +172,55 @@ def test_tuner_times_per_plan_route(zm):
     b.close()
 
 
+_TUNE_SCRIPT = r"""
+import json, sys, torch
+import paper_2304_14492_amd as zm
+import synth
+plan = zm.Plan(40, 320, 320, dtype="f32")
+st = torch.stack([torch.from_numpy(synth.make_frame(synth.FrameSpec(320, 320, blobs=4), seed=k))
+                  for k in range(4)]).cuda()
+b = zm.Batch([plan] * 4, [st[k] for k in range(4)], autotune=True)
+b.run()
+b.check()
+ok = all(torch.equal(b.outs[k], plan.moments(st[k])) for k in range(4))
+print(json.dumps(dict(b.config(), ok=ok)))
+"""
+
+
+def _tune_run(tmp_path, cache):
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, ZM_TUNE_CACHE=str(cache), PYTHONPATH=root)
+    r = subprocess.run([sys.executable, "-c", _TUNE_SCRIPT], cwd=root, env=env, capture_output=True, text=True,
+                       timeout=240)
+    assert r.returncode == 0, r.stderr[-3000:]
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def test_tune_cache_file_routes(zm, tmp_path):
+    """ZM_TUNE_CACHE: a tuned batch appends '<grid> <order> <route> <signature>';
+    a later process takes its shape from the file, in that form or in the
+    older two-field form (persistent kernel), and the moments stay exact."""
+    cache = tmp_path / "tune.txt"
+    first = _tune_run(tmp_path, cache)
+    assert first["ok"]
+    lines = [ln for ln in cache.read_text().splitlines() if ln.strip()]
+    assert len(lines) == 1
+    grid, order, route, sig = lines[0].split(" ", 3)
+    assert int(grid) > 0 and order in ("0", "1") and route in ("0", "1") and sig.startswith("gfx")
+    # the file's choice is taken as written: per-plan launches, item order 1
+    cache.write_text(f"{grid} 1 1 {sig}\n")
+    forced = _tune_run(tmp_path, cache)
+    assert forced["ok"] and forced["route"] == "per_plan" and forced["grid"] == 0 and forced["order"] == 1
+    # the two-field form names a persistent-kernel shape
+    cache.write_text(f"384 1 {sig}\n")
+    old = _tune_run(tmp_path, cache)
+    assert old["ok"] and old["route"] == "persistent" and old["grid"] == 384 and old["order"] == 1
+
+
 @pytest.mark.parametrize("specs", [
     [(192, 20, 11)],                    # one small frame: fewer tiles than the 8 queue ranges
     [(192, 20, 12), (320, 40, 13)],     # two plans, a few tiles each
