@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cstddef>
+#include <cstdint>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -494,11 +495,12 @@ long long group_stride(const zm_batch_s* b, int g) {
     const zm_plan_s* p = b->plans[m[0]];
     const long long hw = (long long)p->H * p->W;
     if (m.size() == 1) return hw;
-    const char* base = (const char*)b->hjobs[m[0]].fa.src;
-    const long long d = (long long)((const char*)b->hjobs[m[1]].fa.src - base);
+    // addresses compared as integers: the frames may be separate allocations
+    auto addr = [&](int k) { return (long long)(uintptr_t)b->hjobs[m[k]].fa.src; };
+    const long long d = addr(1) - addr(0);
     if (d <= 0 || d % (long long)sizeof(float) != 0 || d / (long long)sizeof(float) < hw) return -1;
     for (size_t k = 2; k < m.size(); ++k)
-        if ((long long)((const char*)b->hjobs[m[k]].fa.src - base) != (long long)k * d) return -1;
+        if (addr((int)k) - addr(0) != (long long)k * d) return -1;
     return d / (long long)sizeof(float);
 }
 
