@@ -76,7 +76,7 @@ typedef enum { ZM_RING_MIDPOINT = 0, ZM_RING_GAUSS_LEGENDRE = 1 } zm_ring_rule;
 
 typedef struct {
     int n_max;         /* maximum order, 0..500 (moments: 0..255)                      */
-    int H, W;          /* frame rows, cols (>= 2 each)                                 */
+    int H, W;          /* frame rows, cols (>= 2 each; H * W * element size < 2^31 bytes) */
     zm_dtype dtype;
     int neumann;       /* nonzero: divide by eps_m (eq. (14)-(15))                     */
     int rings;         /* R; 0 selects floor(D/2)                                      */

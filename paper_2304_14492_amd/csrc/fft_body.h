@@ -163,9 +163,13 @@ __device__ __forceinline__ Real bilinear_idx(const Real* __restrict__ img, int H
         v10 = (iin1 && jin0) ? t10 : (Real)0;
         v11 = (iin1 && jin1) ? t11 : (Real)0;
     } else {
-        // two rows of two adjacent taps: each row is one 8-byte load
-        const Real* r0p = img + (i0 * W + j0);
-        const Real* r1p = r0p + W;
+        // two rows of two adjacent taps: each row is one 8-byte load, addressed
+        // by a 32-bit byte offset from the frame (so the load takes the frame
+        // base from scalar registers and one 32-bit offset per lane; frames
+        // are below 2^31 bytes)
+        const char* base = reinterpret_cast<const char*>(img);
+        const Real* r0p = reinterpret_cast<const Real*>(base + (unsigned)((i0 * W + j0) * (int)sizeof(Real)));
+        const Real* r1p = reinterpret_cast<const Real*>(base + (unsigned)((i0 * W + j0 + W) * (int)sizeof(Real)));
         v00 = r0p[0];
         v01 = r0p[1];
         v10 = r1p[0];

@@ -275,6 +275,9 @@ zm_status zm_plan_ex(const zm_plan_desc* d, zm_plan_t* out) {
         return fail(ZM_EINVAL, "n_max must be in [0, " + std::to_string(kMaxTableOrder) + "]");
     if (d->H < 2 || d->W < 2) return fail(ZM_EINVAL, "frame must be at least 2 x 2");
     if (d->dtype < ZM_F64 || d->dtype > ZM_F16X2) return fail(ZM_EINVAL, "unknown dtype");
+    // the kernels address a frame's pixels by 32-bit offsets
+    if ((long long)d->H * d->W * (d->dtype == ZM_F64 ? 8 : 4) >= (1LL << 31))
+        return fail(ZM_EINVAL, "frame must be smaller than 2^31 bytes (H * W * element size)");
     if (d->rule != ZM_RING_MIDPOINT && d->rule != ZM_RING_GAUSS_LEGENDRE) return fail(ZM_EINVAL, "unknown ring rule");
     const int D = std::min(d->H, d->W);
     const int R = d->rings > 0 ? d->rings : D / 2;

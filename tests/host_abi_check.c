@@ -79,6 +79,14 @@ static void check_null_arguments(void) {
     d.angles = 0;
     d.n_max = 501;
     CHECK(zm_plan_ex(&d, &p) == ZM_EINVAL && p == NULL);
+    /* frames of 2^31 bytes or more are rejected (32-bit pixel offsets) */
+    d.n_max = 20;
+    d.H = 16384;
+    d.W = 32768;
+    CHECK(zm_plan_ex(&d, &p) == ZM_EINVAL && p == NULL);
+    d.W = 16384;
+    d.dtype = ZM_F64;
+    CHECK(zm_plan_ex(&d, &p) == ZM_EINVAL && p == NULL);
 }
 
 static void* worker(void* arg) {
