@@ -255,6 +255,12 @@ def test_resampler_alone(zm, H, W, nmax, R, A, dtype):
         # FP32: the fractions and the three lerps rounded in FP32
         scale = max(1.0, float(np.abs(frames[b]).max()))
         assert err <= (1e-12 if dtype == "f64" else 1e-6) * scale, (dtype, b, err)
+    # frames at a stride larger than H * W (every other slice of a larger array)
+    spaced = torch.zeros(2 * B, H, W, dtype=dev.dtype, device="cuda")
+    spaced[::2].copy_(dev)
+    Ps = plan.resample_polar(spaced[::2])
+    torch.cuda.synchronize()
+    assert torch.equal(Ps, P)
     with pytest.raises(RuntimeError):
         zm.Plan(10, 64, 64, dtype="f32", rings=16, angles=128).resample_polar(torch.zeros(1, 64, 64, device="cuda"))
 
