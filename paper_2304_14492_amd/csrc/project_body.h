@@ -188,12 +188,22 @@ __device__ __forceinline__ void project_unit(const ProjArgs& a, int unit, int la
         const float* F = (const float*)Fv;
         // operand fragments run two ring steps ahead of the MFMAs
         float4 a1[2] = {}, b1[2] = {}, a2[2] = {}, b2[2] = {};
+        // operands addressed by 32-bit byte offsets from a wave-uniform base (the
+        // loads then take the base from scalar registers): the table from its
+        // start, the spectra from the column block's first frame (the block's
+        // 16 frames span far less than 2^32 bytes)
+        const char* Tb = (const char*)T;
+        const size_t fbase = (size_t)(__builtin_amdgcn_readfirstlane(cb) * 16) * nRT * M * 2 * zm::kRingTile;
+        const char* Fb = (const char*)(F + fbase);
+        const unsigned ta0 = (unsigned)(aoff[0] * 4), ta1 = (unsigned)(aoff[1] * 4);
+        const unsigned fb0 = (unsigned)((boff[0] - fbase) * 4), fb1 = (unsigned)((boff[1] - fbase) * 4);
         auto load = [&](int k0, float4* ar, float4* br) {
-            const int kk = k0 + 4 * lg;
-            ar[0] = *(const float4*)(T + aoff[0] + (size_t)kk * 16);
-            ar[1] = two ? *(const float4*)(T + aoff[1] + (size_t)kk * 16) : float4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int u = 0; u < 2; ++u) br[u] = *(const float4*)(F + boff[u] + (size_t)(k0 >> 4) * TS + 4 * lg);
+            const unsigned ko = (unsigned)(k0 + 4 * lg) * 64u;
+            ar[0] = *(const float4*)(Tb + (ta0 + ko));
+            ar[1] = two ? *(const float4*)(Tb + (ta1 + ko)) : float4{0.f, 0.f, 0.f, 0.f};
+            const unsigned fo = (unsigned)(k0 >> 4) * (unsigned)(TS * 4) + (unsigned)(16 * lg);
+            br[0] = *(const float4*)(Fb + (fb0 + fo));
+            br[1] = *(const float4*)(Fb + (fb1 + fo));
         };
         if (kb < ke) load(kb, a1, b1);
         if (kb + 16 < ke) load(kb + 16, a2, b2);
